@@ -1,0 +1,205 @@
+/*
+ * mecuco.h -- C ABI of libmecuco.so, the MI355X (gfx950) mean-curvature hot path.
+ *
+ * The method (Levada, "Efficient Mean Curvature Computation on High-Dimensional
+ * Data Manifolds", arXiv 2606.06329) takes a point cloud X in R^{n x m} and a
+ * neighbourhood size k and returns one mean-curvature score per point
+ * (Algorithm 1, "MeCuCo").  The library splits that call at its natural seam:
+ *
+ *   mc_knn               the kNN graph (Step 1, eq. knn; Algorithm 1 kNN-Graph)
+ *   mc_curvature_fast    the Fast branch of Algorithm 1 per point (eq. fast_curv)
+ *   mc_curvature_exact   Theorem 1 per point with a canonical null-space basis
+ *   mc_curvature_backward  gradient of sum_i w_i kappa_i w.r.t. X (lists held fixed)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array pointer is a DEVICE pointer owned by the caller.  The library
+ *    allocates nothing; scratch memory is the caller's workspace `ws` of at
+ *    least mc_workspace_bytes(...) bytes (256-byte aligned).
+ *  - X is float32, row-major, n rows of m values with row stride ldx >= m
+ *    (in elements).  Neighbour lists are int32, n rows of k entries.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls only enqueue
+ *    work on it; they never synchronise (except MC_STRICT, below).
+ *  - All argument checks run on the host before anything is enqueued; a
+ *    failing check returns a positive MC_E* code and enqueues nothing.
+ *  - Numerical trouble never fails a call: it is reported per point through
+ *    the optional uint8 flag arrays (MC_PF_* bits).  With MC_STRICT in `flags`
+ *    the call synchronises the stream and returns MC_ENUMERIC if any point
+ *    carries a flag bit other than MC_PF_KNN_AMBIGUOUS.
+ *  - Calls on different streams are independent; calls sharing a workspace
+ *    must be ordered on one stream.
+ *
+ * Readings of the paper fixed by this ABI (the paper is silent on them)
+ *  - A point is not its own neighbour (MC_INCLUDE_SELF makes it the first
+ *    entry, followed by k-1 others); ties in distance go to the smaller index.
+ *  - The patch is centred at the mean of its k rows; covariances use 1/(k-1).
+ *  - p = k-1 range directions, reduced to the numerical rank when the patch is
+ *    rank deficient (flag MC_PF_RANK_DEFICIENT); q = m - p_eff; q = 0 gives
+ *    t_null = 0.
+ */
+#ifndef MECUCO_H
+#define MECUCO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MC_VERSION 100 /* 1.0.0 */
+#define MC_KMAX 32     /* largest supported k */
+
+/* status codes */
+#define MC_OK 0
+#define MC_EINVAL 1      /* null pointer, k < 2, k > MC_KMAX, k >= n, n or m <= 0, ldx < m, bad enum */
+#define MC_ESHAPE 2      /* size beyond the int32 index range */
+#define MC_EPRECISION 3  /* precision not available for this operation */
+#define MC_EWORKSPACE 4  /* ws_bytes smaller than mc_workspace_bytes(...) or ws misaligned */
+#define MC_ELAUNCH 5     /* a kernel launch failed (hipGetLastError) */
+#define MC_ENUMERIC 6    /* MC_STRICT: some point carries a flag */
+#define MC_EDEVICE 7     /* no usable gfx950 device current */
+
+/* precision of the MFMA stages (distance GEMM, patch moments) */
+#define MC_FP32 0 /* float32 inputs, float32 accumulation */
+#define MC_BF16 1 /* bfloat16 inputs, float32 accumulation */
+#define MC_FP8 2  /* OCP e4m3 inputs with per-row scales (mc_knn only), float32 accumulation */
+
+/* reading of the Fast-mode null-space term */
+#define MC_FAST_PAPER 0 /* Algorithm 1 / eqs. tnull, tA, tB as printed: t_B uses ||X_c V_r||^2, denominator D-p */
+#define MC_FAST_HAAR 1  /* exact expectation of eq. gnull_exp: t_B uses sum X_c^2 (V_r o V_r)1, denominator D-p+2 */
+
+/* flags argument bits */
+#define MC_INCLUDE_SELF 1u /* mc_knn: the point itself is its first neighbour */
+#define MC_STRICT 2u       /* turn per-point flags into MC_ENUMERIC (synchronises) */
+
+/* per-point flag bits (uint8) */
+#define MC_PF_NONFINITE 1u       /* a patch value is NaN/Inf, or idx out of range; kappa = NaN */
+#define MC_PF_DEGENERATE 2u      /* tau = 0 (all k points equal); kappa = 0 */
+#define MC_PF_RANK_DEFICIENT 4u  /* numerical rank of the patch below k-1 */
+#define MC_PF_JACOBI_MAXSWEEPS 8u /* k x k eigen-solve hit its sweep limit */
+#define MC_PF_KNN_AMBIGUOUS 16u  /* k-th and (k+1)-th distances within float32 rounding of each other */
+#define MC_PF_KNN_UNCERTIFIED 32u /* the candidate set could not be proven to contain the k nearest */
+
+/* operations for mc_workspace_bytes */
+#define MC_OP_KNN 0
+#define MC_OP_FAST 1
+#define MC_OP_EXACT 2
+#define MC_OP_BACKWARD 3
+
+/*
+ * mc_knn -- k nearest neighbours of every point by brute force (Step 1, eq. knn).
+ *
+ * Distances are Euclidean.  A tiled MFMA GEMM on globally mean-centred copies of
+ * X (precision: MC_FP32, MC_BF16, or MC_FP8 with per-row scales) proposes
+ * K' = rerank_factor * k candidates per point; they are re-ranked with float32
+ * difference-form distances sum_a (x_a - y_a)^2 on the original X and the k
+ * smallest are kept, ordered by (distance, index).  With rerank_factor == 1 the
+ * GEMM distances decide (MC_FP32 only).
+ *
+ *   X            [n x ldx] float32, device
+ *   n, m, ldx    points, dimensions, row stride (elements)
+ *   k            neighbours per point, 2 <= k <= MC_KMAX, k < n
+ *   precision    MC_FP32 | MC_BF16 | MC_FP8
+ *   rerank_factor 1..4 (K' = rerank_factor * k must not exceed 64 and must be < n)
+ *   flags        MC_INCLUDE_SELF | MC_STRICT
+ *   idx_out      [n x k] int32, device, written
+ *   d2_out       [n x k] float32 squared distances (float32 difference form), or NULL
+ *   knn_flags    [n] uint8 (MC_PF_KNN_* bits), or NULL
+ *   ws, ws_bytes workspace, >= mc_workspace_bytes(MC_OP_KNN, n, m, k, precision, rerank_factor)
+ *   stream       hipStream_t
+ */
+int mc_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int32_t k, int32_t precision,
+           int32_t rerank_factor, uint32_t flags, int32_t* idx_out, float* d2_out,
+           uint8_t* knn_flags, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * mc_curvature_fast -- Fast branch of Algorithm 1 for every point (eq. fast_curv).
+ *
+ * For point i the patch is X[idx[i][0..k-1]], centred at its mean.  tau, the
+ * range term t_range = ||X_c V_r^{o2}||^2/(k-1), t_A, t_B and t_null are those
+ * of Algorithm 1 in the reading `variant`; kappa_i = |(t_range + t_null)/2 + tau/2|.
+ * The truncated SVD comes from the k x k Gram matrix X_c X_c^T (eq. svd_cov);
+ * all terms are evaluated in Gram space from one pass over the patch.
+ *
+ *   X, n, m, ldx  as in mc_knn (any float32 matrix; need not be the kNN input)
+ *   idx          [n x k] int32 neighbour lists, device; entries outside [0, n)
+ *                give kappa = NaN and MC_PF_NONFINITE for that point
+ *   k            2 <= k <= MC_KMAX
+ *   precision    MC_FP32 | MC_BF16 (patch moments on MFMA; eigen-solve and the
+ *                combination are float64 in both)
+ *   variant      MC_FAST_PAPER | MC_FAST_HAAR
+ *   kappa_out    [n] float32, device, written
+ *   flags_out    [n] uint8 (MC_PF_* bits), or NULL
+ *   flags        0 | MC_STRICT
+ */
+int mc_curvature_fast(const float* X, int64_t n, int64_t m, int64_t ldx, const int32_t* idx,
+                      int32_t k, int32_t precision, int32_t variant, uint32_t flags,
+                      float* kappa_out, uint8_t* flags_out, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/*
+ * mc_curvature_exact -- Theorem 1 (eq. kappa_final) for every point with
+ * W = [V_r | Q_null], where Q_null is the canonical completion of V_r: the
+ * trailing m - p_eff columns of the Householder QR of V_r (LAPACK reflector
+ * convention beta = -sign(alpha) ||x||).  The paper's Exact branch uses
+ * whatever null basis its eigensolver returns; because only columns with a
+ * non-zero eigenvalue are weighted, kappa depends on that choice whenever
+ * m > rank, and this ABI fixes it so results are reproducible.
+ *
+ * Arguments as mc_curvature_fast without `variant`; precision MC_FP32 only.
+ */
+int mc_curvature_exact(const float* X, int64_t n, int64_t m, int64_t ldx, const int32_t* idx,
+                       int32_t k, int32_t precision, uint32_t flags, float* kappa_out,
+                       uint8_t* flags_out, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * mc_curvature_backward -- adjoint of mc_curvature_fast (MC_FP32 path):
+ * grad_X += d(sum_i grad_kappa[i] * kappa_i)/dX with the neighbour lists held
+ * fixed.  The derivative of the eigenvectors of the Gram matrix uses
+ * regularised gap factors Delta/(Delta^2 + eta^2), eta = gap_eps * sigma_1;
+ * gap_eps = 0 gives the exact derivative.
+ *
+ *   grad_kappa   [n] float32, device
+ *   grad_X       [n x ldx] float32, device, ACCUMULATED into (atomic adds)
+ */
+int mc_curvature_backward(const float* X, int64_t n, int64_t m, int64_t ldx, const int32_t* idx,
+                          int32_t k, int32_t variant, const float* grad_kappa, float gap_eps,
+                          float* grad_X, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Stage timers (instrumentation, off by default).  While enabled, every kernel
+ * the library launches is bracketed by a pair of hipEvents recorded on the
+ * stream it is launched on.  mc_timing_read synchronises those events, returns
+ * the summed duration (ms) and launch count of one stage since the last read
+ * of that stage, and resets it.  Stages are numbered 0 .. MC_STAGE_COUNT-1.
+ */
+#define MC_STAGE_KNN_COLSUM 0
+#define MC_STAGE_KNN_MEAN 1
+#define MC_STAGE_KNN_CENTER 2
+#define MC_STAGE_KNN_STATS 3
+#define MC_STAGE_KNN_GEMM_TOPK 4
+#define MC_STAGE_KNN_RERANK 5
+#define MC_STAGE_CURV_FAST 6
+#define MC_STAGE_CURV_EXACT 7
+#define MC_STAGE_CURV_BACKWARD 8
+#define MC_STAGE_COUNT 9
+int mc_timing_enable(int on);
+int mc_timing_read(int32_t stage, double* total_ms, int64_t* launches);
+const char* mc_stage_name(int32_t stage);
+
+/* Workspace bytes needed by operation `op` (MC_OP_*) for these sizes (0 if invalid). */
+size_t mc_workspace_bytes(int32_t op, int64_t n, int64_t m, int32_t k, int32_t precision,
+                          int32_t rerank_factor);
+
+/* Static, NUL-terminated description of a status code. */
+const char* mc_status_string(int status);
+
+/* MC_VERSION of the loaded library. */
+int mc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MECUCO_H */

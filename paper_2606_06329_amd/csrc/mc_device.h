@@ -1,0 +1,73 @@
+// Device helpers shared by the gfx950 kernels of libmecuco (wave64, MFMA, LDS).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mc {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef short shortx8 __attribute__((ext_vector_type(8)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+
+constexpr int WAVE = 64;
+
+// Per-point flag bits (mirror MC_PF_* of the public header).
+constexpr uint8_t PF_NONFINITE = 1u;
+constexpr uint8_t PF_DEGENERATE = 2u;
+constexpr uint8_t PF_RANK_DEFICIENT = 4u;
+constexpr uint8_t PF_JACOBI_MAXSWEEPS = 8u;
+constexpr uint8_t PF_KNN_AMBIGUOUS = 16u;
+constexpr uint8_t PF_KNN_UNCERTIFIED = 32u;
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, WAVE));
+  return v;
+}
+
+// Round-to-nearest-even float -> bfloat16 bits (finite inputs).
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// D(16x16) += A(16x4) * B(4x16), fp32.  Lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; it receives D[4*(l/16)+r][l%16], r = 0..3.
+__device__ __forceinline__ floatx4 mfma16x16x4(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// D(32x32) += A(32x2) * B(2x32), fp32.  Lane l supplies A[l%32][l/32] and
+// B[l/32][l%32]; it receives D[8*(r/4) + 4*(l/32) + r%4][l%32], r = 0..15.
+__device__ __forceinline__ floatx16 mfma32x32x2(float a, float b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+// D(16x16) += A(16x32) * B(32x16), bf16 in, fp32 accumulate.  Lane l supplies
+// A[l%16][8*(l/16)+e] and B[8*(l/16)+e][l%16], e = 0..7.
+__device__ __forceinline__ floatx4 mfma16x16x32bf16(shortx8 a, shortx8 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(__attribute__((ext_vector_type(8))) __bf16, a),
+                                                 __builtin_bit_cast(__attribute__((ext_vector_type(8))) __bf16, b),
+                                                 c, 0, 0, 0);
+}
+
+}  // namespace mc

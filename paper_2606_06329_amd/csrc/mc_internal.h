@@ -1,0 +1,47 @@
+// Internal launcher interface between the C-ABI layer (mc_abi.cpp) and the
+// HIP kernels.  Host code only; no device code is declared here.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+namespace mc {
+
+// Stage timers (mc_timing.cpp): no-ops unless mc_timing_enable(1) was called.
+void timing_begin(int stage, hipStream_t s);
+void timing_end(int stage, hipStream_t s);
+
+// Workspace layout helpers (bytes, 256-aligned pieces).
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct KnnPlan {
+  int64_t n, m;
+  int k, kc;          // neighbours, candidates kept per query (rerank_factor * k)
+  int precision;
+  int splits;         // database splits of the GEMM/top-k stage
+  size_t off_xc, off_norm, off_colsum, off_stats, off_cand_s, off_cand_j, off_xlow, off_scale, total;
+};
+
+KnnPlan knn_plan(int64_t n, int64_t m, int k, int kc, int precision);
+
+// Fast curvature: dynamic LDS bytes and launch of the fused per-point kernel.
+hipError_t launch_curv_fast(const float* X, int64_t n, int64_t m, int64_t ldx, const int32_t* idx,
+                            int k, int precision, int variant, float* kappa, uint8_t* flags,
+                            hipStream_t stream);
+
+hipError_t launch_curv_exact(const float* X, int64_t n, int64_t m, int64_t ldx, const int32_t* idx,
+                             int k, float* kappa, uint8_t* flags, void* ws, hipStream_t stream);
+
+size_t curv_exact_ws_bytes(int64_t n, int64_t m, int k);
+
+hipError_t launch_curv_backward(const float* X, int64_t n, int64_t m, int64_t ldx,
+                                const int32_t* idx, int k, int variant, const float* gk,
+                                float gap_eps, float* grad, hipStream_t stream);
+
+hipError_t launch_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int k, int kc,
+                      int precision, bool include_self, int32_t* idx, float* d2, uint8_t* kflags,
+                      void* ws, const KnnPlan& plan, hipStream_t stream);
+
+}  // namespace mc

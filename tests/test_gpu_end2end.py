@@ -1,0 +1,50 @@
+"""End-to-end GPU path (kNN then Fast curvature) against the oracle, small and full size."""
+import numpy as np
+import pytest
+
+from oracle import knn as ok
+from paper_2606_06329_amd import synth
+from tests.gpu_common import TOL_FP32, TOL_LOW, knn_set_report, oracle_fast, rel_err, to_dev
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def test_sphere_all_points():
+    """The 500-point sphere workload, every point, both readings."""
+    import paper_2606_06329_amd as P
+    X, k = synth.make("sphere")
+    kap_p, idx, fl = P.curvature(to_dev(X), k, mode="fast", variant="paper")
+    kap_h, _, _ = P.curvature(to_dev(X), k, mode="fast", variant="haar", idx=idx)
+    idx = idx.cpu().numpy()
+    bad_big, _, _, oidx = knn_set_report(idx, X, np.arange(500), k)
+    assert bad_big == 0
+    for kap, v in ((kap_p, "paper"), (kap_h, "haar")):
+        want, pe = oracle_fast(X, idx, v)
+        ok_rows = (fl.cpu().numpy() & 4) == 0
+        assert rel_err(kap.cpu().numpy(), want)[ok_rows].max() <= TOL_FP32
+
+
+@pytest.mark.parametrize("name", ["clusters", "swissroll", "torus"])
+def test_full_size_sampled(name):
+    """Full-size workload in the benchmark's launch configuration; 48 sampled points are
+    checked against the oracle (kNN rows and curvature one by one)."""
+    import paper_2606_06329_amd as P
+    X, k = synth.make(name)
+    n = X.shape[0]
+    print(f"full size {name} n={n} m={X.shape[1]} k={k}", flush=True)
+    Xd = to_dev(X)
+    idx, d2, kfl = P.knn(Xd, k, precision="fp32", rerank=2)
+    kap, fl = P.curvature_fast(Xd, idx, "paper", "fp32")
+    idx = idx.cpu().numpy()
+    kap = kap.cpu().numpy()
+    fl = (fl | kfl).cpu().numpy()
+    rows = np.random.default_rng(42).choice(n, 48, replace=False)
+    bad_big, bad_small, nbig, _ = knn_set_report(idx, X, rows, k)
+    assert bad_big == 0
+    want, pe = oracle_fast(X, idx, "paper", rows=rows)
+    okr = (fl[rows] & 4) == 0
+    assert rel_err(kap[rows], want)[okr].max() <= TOL_FP32
+    # property at every point: kappa finite and non-negative
+    assert np.all(np.isfinite(kap)) and np.all(kap >= 0)
+    print(f"  uncertified {(fl & 32).astype(bool).mean():.4f}, rank-deficient {(fl & 4).astype(bool).mean():.4f}")

@@ -1,0 +1,86 @@
+"""GPU parity of mc_knn against the oracle's brute-force kNN.
+
+Sets must agree exactly wherever the oracle's gap between the k-th and (k+1)-th
+distance exceeds the float32 rounding bound; other rows are counted and
+reported.  Distances are compared with the float64 values.
+"""
+import numpy as np
+import pytest
+
+from oracle import knn as ok
+from paper_2606_06329_amd import synth
+from tests.gpu_common import knn_set_report, to_dev
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # name, n, m, k, precision, rerank
+    ("sphere", 500, 20, 10, "fp32", 2),
+    ("swissroll", 1300, 128, 12, "fp32", 2),
+    ("clusters", 1000, 784, 11, "fp32", 2),
+    ("torus", 2100, 256, 16, "fp32", 2),
+    ("swissroll", 777, 61, 7, "fp32", 1),    # ragged n and m, no re-rank
+    ("blobs", 900, 300, 32, "fp32", 2),      # K' = 64
+    ("torus", 2100, 256, 16, "bf16", 2),
+    ("clusters", 1000, 784, 11, "bf16", 2),
+    ("swissroll", 1300, 128, 12, "bf16", 3),
+]
+
+
+@pytest.mark.parametrize("name,n,m,k,prec,rr", CASES,
+                         ids=[f"{c[0]}-{c[1]}x{c[2]}-k{c[3]}-{c[4]}-r{c[5]}" for c in CASES])
+def test_knn_sets(name, n, m, k, prec, rr):
+    import paper_2606_06329_amd as P
+    gen = synth.WORKLOADS[name][0]
+    X = gen(n=n, m=m, seed=77)
+    print(f"knn {name} n={n} m={m} k={k} {prec} rerank={rr}", flush=True)
+    idx, d2, fl = P.knn(to_dev(X), k, precision=prec, rerank=rr)
+    idx = idx.cpu().numpy()
+    d2 = d2.cpu().numpy()
+    fl = fl.cpu().numpy()
+    rows = np.arange(n)
+    bad_big, bad_small, nbig, oidx = knn_set_report(idx, X, rows, k)
+    print(f"  mismatches: {bad_big} (gap above bound, of {nbig}), {bad_small} (below); "
+          f"uncertified {(fl & 32).astype(bool).sum()}, ambiguous {(fl & 16).astype(bool).sum()}")
+    assert bad_big == 0
+    # the ordered lists agree where the whole list is well separated, distances are float32-accurate
+    X64 = X.astype(np.float64)
+    for i in range(0, n, 13):
+        dd = ((X64[idx[i]] - X64[i]) ** 2).sum(1)
+        assert np.allclose(d2[i], dd, rtol=1e-5, atol=1e-6 * dd.max())
+        assert np.all(np.diff(d2[i]) >= 0)
+        assert i not in idx[i]
+
+
+def test_knn_include_self():
+    import paper_2606_06329_amd as P
+    X = synth.swissroll(n=600, m=24, seed=5)
+    X[10] = X[3]                                     # a duplicate with a smaller index
+    idx, d2, _ = P.knn(to_dev(X), 8, include_self=True)
+    idx = idx.cpu().numpy()
+    assert np.all(idx[:, 0] == np.arange(600))
+    assert idx[10, 1] == 3 and idx[3, 1] == 10
+
+
+def test_knn_duplicates_tie_order():
+    """Exact duplicates (distance 0) are valid neighbours, ordered by index."""
+    import paper_2606_06329_amd as P
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((300, 16)).astype(np.float32)
+    X[[50, 20, 200]] = X[100]
+    idx, d2, _ = P.knn(to_dev(X), 5)
+    idx, d2 = idx.cpu().numpy(), d2.cpu().numpy()
+    assert list(idx[100][:3]) == [20, 50, 200]
+    assert np.all(d2[100][:3] == 0.0)
+
+
+def test_knn_translation_invariant_sets():
+    import paper_2606_06329_amd as P
+    X = synth.torus(n=1500, m=64, seed=9)
+    a, _, fa = P.knn(to_dev(X), 10)
+    b, _, fb = P.knn(to_dev(X + np.float32(3.0)), 10)
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    amb = ((fa | fb).cpu().numpy() & 16) != 0
+    same = np.array([set(a[i]) == set(b[i]) for i in range(1500)])
+    assert np.all(same | amb)

@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--variant", default="paper", choices=["paper", "haar"])
     ap.add_argument("--rerank", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -88,6 +90,13 @@ def main():
         kap, fl = P.curvature_fast(Xd, idx, args.variant, prec)
         return idx, kap, fl | kfl
 
+    if args.copy_calibration:
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)                 # reads and writes exactly 256 MiB
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()

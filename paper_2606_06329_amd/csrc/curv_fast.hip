@@ -1,4 +1,4 @@
-// Fused Fast-mode mean curvature, one workgroup per point (gfx950).
+// Fused Fast-mode mean curvature, one point per wave (k <= 20) or per workgroup (gfx950).
 //
 // What is computed (Fast branch of Algorithm 1, eqs. tnull/tA/tB/fast_curv):
 // for the centred k x m patch X_c of point i,
@@ -40,13 +40,15 @@ struct FastCfg {
   static constexpr int ROWS = (16 * MB > KMAX + 3) ? 16 * MB : KMAX + 3;
   static constexpr int NPC = KMAX * (KMAX + 1) / 2 + 1;     // pair columns + ones column
   static constexpr int NB = (NPC + 15) / 16;                // 16-column blocks of the RHS
-  static constexpr int NW = KMAX <= 20 ? 1 : (KMAX <= 26 ? 2 : 4);
+  static constexpr int NW = KMAX <= 20 ? 1 : (KMAX <= 26 ? 2 : 4);   // waves per point
+  static constexpr int PPW = NW == 1 ? 4 : 1;               // points per workgroup
+  static constexpr int NTG = NW * WAVE;                     // threads per point
+  static constexpr int NT = PPW * NTG;                      // threads per workgroup
   static constexpr int NBW = (NB + NW - 1) / NW;            // RHS blocks per wave
-  static constexpr int NT = NW * WAVE;
   static constexpr int KK = (KMAX + 1) & ~1;                // even Jacobi size
   static constexpr int JLD = KK + 1;                        // Jacobi row stride (doubles)
   static constexpr int NPAD = NB * 16;
-  // LDS layout (bytes); the staged chunk and the moments share storage.
+  // LDS layout of one point (bytes); the staged chunk and the moments share storage.
   static constexpr size_t LHS_B = (size_t)ROWS * FLDX * 4;
   static constexpr size_t MOM_B = (size_t)(KMAX + 2) * NPAD * 4;
   static constexpr size_t U0_B = LHS_B > MOM_B ? LHS_B : MOM_B;
@@ -55,11 +57,12 @@ struct FastCfg {
   static constexpr size_t OFF_UT = OFF_JV + (size_t)KK * JLD * 8;
   static constexpr size_t OFF_Y = OFF_UT + (size_t)KMAX * KMAX * 8;
   static constexpr size_t OFF_RED = OFF_Y + (size_t)KMAX * KMAX * 8;     // 16 doubles x NW
-  static constexpr size_t OFF_ROT = OFF_RED + (size_t)16 * NW * 8;        // c,s per pair
-  static constexpr size_t OFF_INT = OFF_ROT + (size_t)KK * 8;             // ints
-  static constexpr size_t N_INT = KMAX + 3 * KK + KK + 8;
-  static constexpr size_t OFF_PJ = OFF_INT + N_INT * 4;
-  static constexpr size_t BYTES = OFF_PJ + 2 * NPAD;
+  static constexpr size_t OFF_ROT = OFF_RED + (size_t)16 * NW * 8;        // c, s per pair
+  static constexpr size_t OFF_INT = OFF_ROT + (size_t)KK * 8;
+  static constexpr size_t N_INT = KMAX + KK + 8;                          // nb, ord, misc
+  static constexpr size_t OFF_PIDX = OFF_INT + N_INT * 4;
+  static constexpr size_t OFF_PJ = OFF_PIDX + (size_t)KMAX * KMAX * 2;
+  static constexpr size_t BYTES = (OFF_PJ + 2 * NPAD + 15) & ~(size_t)15;
 };
 
 // Index of pair (a, b), a <= b, in row-major upper-triangular order of a k x k matrix.
@@ -68,13 +71,25 @@ __device__ __forceinline__ int pair_index(int a, int b, int k) {
   return a * k - (a * (a - 1)) / 2 + (b - a);
 }
 
-// Block-wide sum of NV doubles per thread; result valid in every thread.
+// Synchronise the threads of one point: a single wave needs only an LDS fence.
+template <int NW>
+__device__ __forceinline__ void gsync() {
+  if constexpr (NW == 1) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// Sum of NV doubles over the threads of one point; result valid in every thread.
 template <int NW, int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
-  const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+__device__ __forceinline__ void group_sum(double (&v)[NV], double* red, int tg) {
 #pragma unroll
   for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
-  if (NW > 1) {
+  if constexpr (NW > 1) {
+    const int w = tg / WAVE, l = tg % WAVE;
     __syncthreads();
     if (l == 0) {
 #pragma unroll
@@ -91,12 +106,12 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
   }
 }
 
-// Stage one chunk: lanes of wave 0 hold column c0+lane of the k gathered rows in xr.
+// Lane `lane` of the staging wave holds column c0+lane of the k gathered rows in xr.
 template <int KMAX>
 __device__ __forceinline__ void load_chunk(float (&xr)[KMAX], const float* __restrict__ X,
                                            int64_t ldx, const int* nb, int k, int64_t m,
-                                           int64_t c0) {
-  const int64_t c = c0 + lane_id();
+                                           int64_t c0, int lane) {
+  const int64_t c = c0 + lane;
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) {
     float v = 0.0f;
@@ -105,12 +120,27 @@ __device__ __forceinline__ void load_chunk(float (&xr)[KMAX], const float* __res
   }
 }
 
+// Player at round-robin position `pos` in round r of the circle schedule on KK players.
+__device__ __forceinline__ int rr_player(int pos, int r, int KK) {
+  if (pos == 0) return 0;
+  int t = pos - 1 + r;
+  if (t >= KK - 1) t -= KK - 1;
+  return t + 1;
+}
+
 template <int KMAX>
 __global__ __launch_bounds__(FastCfg<KMAX>::NT) void curv_fast_kernel(
     const float* __restrict__ X, int64_t n, int64_t m, int64_t ldx, const int32_t* __restrict__ idx,
     int k, int variant, float* __restrict__ kappa_out, uint8_t* __restrict__ flags_out) {
   using C = FastCfg<KMAX>;
-  extern __shared__ __align__(16) unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem_all[];
+  const int gid = threadIdx.x / C::NTG;            // point group inside the workgroup
+  const int tg = threadIdx.x % C::NTG;             // thread inside the group
+  const int w = tg / WAVE;
+  const int lane = tg % WAVE;
+  const int64_t i = (int64_t)blockIdx.x * C::PPW + gid;
+  if (i >= n) return;                              // whole group exits together
+  unsigned char* smem = smem_all + (size_t)gid * C::BYTES;
   float* lhs = reinterpret_cast<float*>(smem);     // ROWS x FLDX (during the m loop)
   float* mom = reinterpret_cast<float*>(smem);     // (k+2) x NPAD (after the m loop)
   double* JA = reinterpret_cast<double*>(smem + C::OFF_JA);
@@ -121,31 +151,25 @@ __global__ __launch_bounds__(FastCfg<KMAX>::NT) void curv_fast_kernel(
   double* ROT = reinterpret_cast<double*>(smem + C::OFF_ROT);   // c[KK/2], s[KK/2]
   int* IN = reinterpret_cast<int*>(smem + C::OFF_INT);
   int* nb = IN;                       // [KMAX] neighbour rows
-  int* who = IN + KMAX;               // [KK] pair id of index x
-  int* rp = who + C::KK;              // [KK/2] p of pair
-  int* rq = rp + C::KK / 2;           // [KK/2] q of pair
-  int* ord = rq + C::KK / 2;          // [KK] eigen order
+  int* ord = IN + KMAX;               // [KK] eigen order
   int* misc = ord + C::KK;            // [8] flags / counters
+  uint16_t* PIDX = reinterpret_cast<uint16_t*>(smem + C::OFF_PIDX);
   unsigned char* pj1 = smem + C::OFF_PJ;
   unsigned char* pj2 = pj1 + C::NPAD;
 
-  const int tid = threadIdx.x;
-  const int w = tid / WAVE;
-  const int lane = tid % WAVE;
-  const int64_t i = blockIdx.x;
   const int np = k * (k + 1) / 2;
   const int npc = np + 1;
   const int nbr = (npc + 15) / 16;    // RHS blocks in use
 
   // ---- setup: neighbour rows, pair tables, zero rows --------------------------------
-  if (tid < 8) misc[tid] = 0;
-  __syncthreads();
-  if (tid < k) {
-    int v = idx[i * k + tid];
+  if (tg < 8) misc[tg] = 0;
+  gsync<C::NW>();
+  if (tg < k) {
+    int v = idx[i * k + tg];
     if (v < 0 || (int64_t)v >= n) { misc[0] = 1; v = 0; }
-    nb[tid] = v;
+    nb[tg] = v;
   }
-  for (int t = tid; t < C::NPAD; t += C::NT) {
+  for (int t = tg; t < C::NPAD; t += C::NTG) {
     int a = k + 2, b = k + 2;          // zero row
     if (t < np) {
       int r = t;
@@ -158,10 +182,11 @@ __global__ __launch_bounds__(FastCfg<KMAX>::NT) void curv_fast_kernel(
     pj1[t] = (unsigned char)a;
     pj2[t] = (unsigned char)b;
   }
-  for (int t = tid; t < (C::ROWS - (k + 2)) * FLDX; t += C::NT) lhs[(k + 2) * FLDX + t] = 0.0f;
-  __syncthreads();
+  for (int t = tg; t < k * k; t += C::NTG) PIDX[(t / k) * KMAX + t % k] = (uint16_t)pair_index(t / k, t % k, k);
+  for (int t = tg; t < (C::ROWS - (k + 2)) * FLDX; t += C::NTG) lhs[(k + 2) * FLDX + t] = 0.0f;
+  gsync<C::NW>();
   if (misc[0]) {
-    if (tid == 0) {
+    if (tg == 0) {
       kappa_out[i] = __builtin_nanf("");
       if (flags_out) flags_out[i] = PF_NONFINITE;
     }
@@ -188,7 +213,7 @@ __global__ __launch_bounds__(FastCfg<KMAX>::NT) void curv_fast_kernel(
   float xr[KMAX];
   double tau64 = 0.0;
   bool nonfinite = false;
-  if (w == 0) load_chunk<KMAX>(xr, X, ldx, nb, k, m, 0);
+  if (w == 0) load_chunk<KMAX>(xr, X, ldx, nb, k, m, 0, lane);
 
   for (int64_t c0 = 0; c0 < m; c0 += FCH) {
     if (w == 0) {
@@ -217,8 +242,8 @@ __global__ __launch_bounds__(FastCfg<KMAX>::NT) void curv_fast_kernel(
       lhs[k * FLDX + lane] = q;
       lhs[(k + 1) * FLDX + lane] = (c0 + lane < m) ? 1.0f : 0.0f;
     }
-    __syncthreads();
-    if (w == 0 && c0 + FCH < m) load_chunk<KMAX>(xr, X, ldx, nb, k, m, c0 + FCH);
+    gsync<C::NW>();
+    if (w == 0 && c0 + FCH < m) load_chunk<KMAX>(xr, X, ldx, nb, k, m, c0 + FCH, lane);
 
     const int64_t rem = m - c0;
     const int steps = rem >= FCH ? FCH / 4 : (int)((rem + 3) / 4);
@@ -236,7 +261,7 @@ __global__ __launch_bounds__(FastCfg<KMAX>::NT) void curv_fast_kernel(
         }
       }
     }
-    __syncthreads();
+    gsync<C::NW>();
   }
 
   // ---- moments to LDS ------------------------------------------------------------
@@ -262,10 +287,10 @@ __global__ __launch_bounds__(FastCfg<KMAX>::NT) void curv_fast_kernel(
         }
     }
   }
-  __syncthreads();
+  gsync<C::NW>();
   const double tauk = RED[15 * C::NW];   // (k-1) * tau, float64 accumulation
   if (misc[1]) {
-    if (tid == 0) {
+    if (tg == 0) {
       kappa_out[i] = __builtin_nanf("");
       if (flags_out) flags_out[i] = PF_NONFINITE;
     }
@@ -273,28 +298,27 @@ __global__ __launch_bounds__(FastCfg<KMAX>::NT) void curv_fast_kernel(
   }
 
   // ---- k x k eigen-solve: cyclic Jacobi, parallel (round-robin) order, float64 -------
+  // Each round rotates KK/2 disjoint planes.  The update works on 2 x 2 blocks of A
+  // (pair i x pair i') and on row x of V restricted to one pair, so every thread
+  // reads and writes the same cells and the update runs in place.
   const int KK = (k + 1) & ~1;
+  const int HP = KK / 2;
   const float* Krow = mom + (k + 1) * C::NPAD;
   double trace = 0.0;
-  for (int e = tid; e < KK * KK; e += C::NT) {
+  for (int e = tg; e < KK * KK; e += C::NTG) {
     const int x = e / KK, y = e % KK;
-    JA[x * C::JLD + y] = (x < k && y < k) ? (double)Krow[pair_index(x, y, k)] : 0.0;
+    JA[x * C::JLD + y] = (x < k && y < k) ? (double)Krow[PIDX[x * KMAX + y]] : 0.0;
     JV[x * C::JLD + y] = (x == y) ? 1.0 : 0.0;
   }
-  for (int x = 0; x < k; ++x) trace += (double)Krow[pair_index(x, x, k)];
-  __syncthreads();
+  for (int x = 0; x < k; ++x) trace += (double)Krow[PIDX[x * KMAX + x]];
+  gsync<C::NW>();
   const double floor_abs = trace * 0x1p-100;
-  constexpr int EPT = (C::KK * C::KK + C::NT - 1) / C::NT;
   int sweep = 0;
   for (; sweep < JAC_MAX_SWEEPS; ++sweep) {
-    if (tid == 0) misc[2] = 0;
-    __syncthreads();
+    if (tg == 0) misc[2] = 0;
     for (int r = 0; r < KK - 1; ++r) {
-      if (tid < KK / 2) {
-        // circle method: position 0 fixed, the other KK-1 rotate by r
-        const int pa = (tid == 0) ? 0 : ((tid - 1 + r) % (KK - 1)) + 1;
-        const int pbp = KK - 1 - tid;
-        const int pb = ((pbp - 1 + r) % (KK - 1)) + 1;
+      if (tg < HP) {
+        const int pa = rr_player(tg, r, KK), pb = rr_player(KK - 1 - tg, r, KK);
         const int p = pa < pb ? pa : pb, q = pa < pb ? pb : pa;
         const double app = JA[p * C::JLD + p], aqq = JA[q * C::JLD + q], apq = JA[p * C::JLD + q];
         double c = 1.0, s = 0.0;
@@ -306,64 +330,65 @@ __global__ __launch_bounds__(FastCfg<KMAX>::NT) void curv_fast_kernel(
           s = t * c;
           misc[2] = 1;
         }
-        ROT[tid] = c;
-        ROT[C::KK / 2 + tid] = s;
-        rp[tid] = p;
-        rq[tid] = q;
-        who[p] = tid;
-        who[q] = tid;
+        ROT[tg] = c;
+        ROT[C::KK / 2 + tg] = s;
       }
-      __syncthreads();
-      double na[EPT], nv[EPT];
-#pragma unroll
-      for (int u = 0; u < EPT; ++u) {
-        const int e = tid + u * C::NT;
-        na[u] = 0.0;
-        nv[u] = 0.0;
-        if (e < KK * KK) {
-          const int x = e / KK, y = e % KK;
-          const int ix = who[x], iy = who[y];
-          const int px = rp[ix], qx = rq[ix], py = rp[iy], qy = rq[iy];
-          const double cx = ROT[ix], sx = ROT[C::KK / 2 + ix];
-          const double cy = ROT[iy], sy = ROT[C::KK / 2 + iy];
-          // row x of J^T A: p-row: c A_p - s A_q ; q-row: s A_p + c A_q
-          const double xp = (x == px) ? cx : sx, xq = (x == px) ? -sx : cx;
-          const double yp = (y == py) ? cy : sy, yq = (y == py) ? -sy : cy;
-          const double app_ = JA[px * C::JLD + py], apq_ = JA[px * C::JLD + qy];
-          const double aqp_ = JA[qx * C::JLD + py], aqq_ = JA[qx * C::JLD + qy];
-          na[u] = xp * (yp * app_ + yq * apq_) + xq * (yp * aqp_ + yq * aqq_);
-          nv[u] = yp * JV[x * C::JLD + py] + yq * JV[x * C::JLD + qy];
-          if (ix == iy && x != y && ROT[C::KK / 2 + ix] != 0.0) na[u] = 0.0;
+      gsync<C::NW>();
+      // A <- J^T A J on 2 x 2 blocks; V <- V J on row pairs
+      for (int u = tg; u < HP * HP + KK * HP; u += C::NTG) {
+        if (u < HP * HP) {
+          const int bi = u / HP, bj = u % HP;
+          const int pa = rr_player(bi, r, KK), pb = rr_player(KK - 1 - bi, r, KK);
+          const int p = pa < pb ? pa : pb, q = pa < pb ? pb : pa;
+          const int qa = rr_player(bj, r, KK), qb = rr_player(KK - 1 - bj, r, KK);
+          const int p2 = qa < qb ? qa : qb, q2 = qa < qb ? qb : qa;
+          const double c = ROT[bi], s = ROT[C::KK / 2 + bi];
+          const double c2 = ROT[bj], s2 = ROT[C::KK / 2 + bj];
+          const double a00 = JA[p * C::JLD + p2], a01 = JA[p * C::JLD + q2];
+          const double a10 = JA[q * C::JLD + p2], a11 = JA[q * C::JLD + q2];
+          // columns: (p2, q2) <- (c2 a_p2 - s2 a_q2, s2 a_p2 + c2 a_q2)
+          const double m00 = c2 * a00 - s2 * a01, m01 = s2 * a00 + c2 * a01;
+          const double m10 = c2 * a10 - s2 * a11, m11 = s2 * a10 + c2 * a11;
+          // rows: (p, q) <- (c m_p - s m_q, s m_p + c m_q)
+          double n00 = c * m00 - s * m10, n01 = c * m01 - s * m11;
+          double n10 = s * m00 + c * m10, n11 = s * m01 + c * m11;
+          if (bi == bj && s != 0.0) {
+            n01 = 0.0;
+            n10 = 0.0;
+          }
+          JA[p * C::JLD + p2] = n00;
+          JA[p * C::JLD + q2] = n01;
+          JA[q * C::JLD + p2] = n10;
+          JA[q * C::JLD + q2] = n11;
+        } else {
+          const int v = u - HP * HP;
+          const int x = v / HP, bj = v % HP;
+          const int qa = rr_player(bj, r, KK), qb = rr_player(KK - 1 - bj, r, KK);
+          const int p2 = qa < qb ? qa : qb, q2 = qa < qb ? qb : qa;
+          const double c2 = ROT[bj], s2 = ROT[C::KK / 2 + bj];
+          const double v0 = JV[x * C::JLD + p2], v1 = JV[x * C::JLD + q2];
+          JV[x * C::JLD + p2] = c2 * v0 - s2 * v1;
+          JV[x * C::JLD + q2] = s2 * v0 + c2 * v1;
         }
       }
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < EPT; ++u) {
-        const int e = tid + u * C::NT;
-        if (e < KK * KK) {
-          const int x = e / KK, y = e % KK;
-          JA[x * C::JLD + y] = na[u];
-          JV[x * C::JLD + y] = nv[u];
-        }
-      }
-      __syncthreads();
+      gsync<C::NW>();
     }
     const int any = misc[2];
-    __syncthreads();
+    gsync<C::NW>();
     if (!any) break;
   }
 
   // ---- eigen order, numerical rank, Ut = U_p / sqrt(sigma) -------------------------------
-  if (tid < KK) {
-    const double dx = JA[tid * C::JLD + tid];
+  if (tg < KK) {
+    const double dx = JA[tg * C::JLD + tg];
     int rk = 0;
     for (int y = 0; y < KK; ++y) {
       const double dy = JA[y * C::JLD + y];
-      rk += (dy > dx) || (dy == dx && y < tid);
+      rk += (dy > dx) || (dy == dx && y < tg);
     }
-    ord[rk] = tid;
+    ord[rk] = tg;
   }
-  __syncthreads();
+  gsync<C::NW>();
   const double sig0 = JA[ord[0] * C::JLD + ord[0]];
   const int plim = (int)((int64_t)(k - 1) < m ? (int64_t)(k - 1) : m);
   const double rtol = (double)(m > k ? m : k) * 0x1p-24;
@@ -371,23 +396,23 @@ __global__ __launch_bounds__(FastCfg<KMAX>::NT) void curv_fast_kernel(
   if (sig0 > 0.0) {
     while (pe < plim && JA[ord[pe] * C::JLD + ord[pe]] > rtol * sig0) ++pe;
   }
-  for (int e = tid; e < k * pe; e += C::NT) {
+  for (int e = tg; e < k * pe; e += C::NTG) {
     const int a = e / pe, l = e % pe;
     const int x = ord[l];
     UT[a * KMAX + l] = JV[a * C::JLD + x] / sqrt(JA[x * C::JLD + x]);
   }
-  __syncthreads();
+  gsync<C::NW>();
 
   // ---- Gram-space terms -------------------------------------------------------------
-  // acc2: 0 t_range, 1 g, 2 t_A, 3 t_S, 4 t_D
+  // part: 0 t_range, 1 g, 2 t_A, 3 t_S, 4 t_D  (each times k-1)
   double part[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const float* Qrow = mom + k * C::NPAD;
   // t_S = sum_l ||K ut_l||^2 ; t_D = sum_l ut_l^T Q ut_l
-  for (int e = tid; e < k * pe; e += C::NT) {
+  for (int e = tg; e < k * pe; e += C::NTG) {
     const int a = e / pe, l = e % pe;
     double kv = 0.0, qv = 0.0;
     for (int b = 0; b < k; ++b) {
-      const int pb = pair_index(a, b, k);
+      const int pb = PIDX[a * KMAX + b];
       const double u = UT[b * KMAX + l];
       kv = fma((double)Krow[pb], u, kv);
       qv = fma((double)Qrow[pb], u, qv);
@@ -397,15 +422,15 @@ __global__ __launch_bounds__(FastCfg<KMAX>::NT) void curv_fast_kernel(
   }
   for (int j = 0; j < k; ++j) {
     const float* Tj = mom + j * C::NPAD;
-    for (int e = tid; e < k * pe; e += C::NT) {
+    for (int e = tg; e < k * pe; e += C::NTG) {
       const int a = e / pe, l = e % pe;
       double yv = 0.0;
-      for (int b = 0; b < k; ++b) yv = fma((double)Tj[pair_index(a, b, k)], UT[b * KMAX + l], yv);
+      for (int b = 0; b < k; ++b) yv = fma((double)Tj[PIDX[a * KMAX + b]], UT[b * KMAX + l], yv);
       YB[a * KMAX + l] = yv;
     }
-    __syncthreads();
+    gsync<C::NW>();
     double trg = 0.0;
-    for (int e = tid; e < pe * pe; e += C::NT) {
+    for (int e = tg; e < pe * pe; e += C::NTG) {
       const int l1 = e / pe, l2 = e % pe;
       double gv = 0.0;
       for (int a = 0; a < k; ++a) gv = fma(UT[a * KMAX + l1], YB[a * KMAX + l2], gv);
@@ -416,16 +441,16 @@ __global__ __launch_bounds__(FastCfg<KMAX>::NT) void curv_fast_kernel(
       }
     }
     double tv[1] = {trg};
-    block_sum<C::NW, 1>(tv, RED);
-    if (tid == 0) {
+    group_sum<C::NW, 1>(tv, RED, tg);
+    if (tg == 0) {
       const double bj = (double)mom[j * C::NPAD + np] - tv[0];   // (X_c d_P)_j
       part[2] = fma(bj, bj, part[2]);
     }
-    __syncthreads();
+    gsync<C::NW>();
   }
-  block_sum<C::NW, 5>(part, RED);
+  group_sum<C::NW, 5>(part, RED, tg);
 
-  if (tid == 0) {
+  if (tg == 0) {
     uint8_t fl = 0;
     const double km1 = (double)(k - 1);
     const double tau = tauk / km1;
@@ -461,13 +486,14 @@ static hipError_t launch_fast_k(const float* X, int64_t n, int64_t m, int64_t ld
   static bool attr_set = false;   // LDS beyond 64 KiB needs the opt-in attribute
   if (!attr_set) {
     hipFuncSetAttribute(reinterpret_cast<const void*>(&curv_fast_kernel<KMAX>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::BYTES);
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)(C::PPW * C::BYTES));
     (void)hipGetLastError();
     attr_set = true;
   }
+  const unsigned grid = (unsigned)((n + C::PPW - 1) / C::PPW);
   timing_begin(6, stream);
-  hipLaunchKernelGGL(curv_fast_kernel<KMAX>, dim3((unsigned)n), dim3(C::NT), C::BYTES, stream, X, n,
-                     m, ldx, idx, k, variant, kappa, flags);
+  hipLaunchKernelGGL(curv_fast_kernel<KMAX>, dim3(grid), dim3(C::NT), C::PPW * C::BYTES, stream, X,
+                     n, m, ldx, idx, k, variant, kappa, flags);
   timing_end(6, stream);
   return hipGetLastError();
 }

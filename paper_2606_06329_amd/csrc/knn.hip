@@ -28,7 +28,8 @@ namespace mc {
 
 constexpr int KBQ = 128;   // queries per tile
 constexpr int KBN = 128;   // database points per tile
-constexpr int KNT = 256;   // threads per GEMM workgroup
+constexpr int KNT = 512;   // threads per GEMM workgroup (8 waves)
+constexpr int RPW = KBQ / (KNT / 64);   // query rows owned by one wave in the top-k stage
 constexpr int SLD = KBN + 4;  // score-tile row stride (floats)
 constexpr int KCMAX = 64;  // largest candidate list
 
@@ -111,18 +112,23 @@ __global__ __launch_bounds__(256) void knn_stats_kernel(const float* __restrict_
 }
 
 // ------------------------------------------------------------------------------------
-// wave-level sorted list: lane r holds the r-th smallest (score, index), r < kc
+// wave-level sorted list: lane r holds the r-th smallest (score, index) of a row,
+// r = 0..63; the row's threshold is the entry of lane kc-1.
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ float rdlane(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-__device__ __forceinline__ void list_insert(float& ls, int& lj, float s, int j, uint64_t kmask) {
+__device__ __forceinline__ bool key_less(float s, int j, float s2, int j2) {
+  return s < s2 || (s == s2 && j < j2);
+}
+
+// Insert one (s, j) that beats the threshold: lanes at or after its rank shift up by one.
+__device__ __forceinline__ void list_insert(float& ls, int& lj, float s, int j) {
   const int lane = lane_id();
-  const bool less = (ls < s) || (ls == s && lj < j);
-  const int pos = __popcll(__ballot(less) & kmask);
-  const float us = __shfl_up(ls, 1, WAVE);
-  const int uj = __shfl_up(lj, 1, WAVE);
+  const int pos = __popcll(__ballot(key_less(ls, lj, s, j)));
+  const float us = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(ls), 0x138, 0xf, 0xf, false));
+  const int uj = __builtin_amdgcn_mov_dpp(lj, 0x138, 0xf, 0xf, false);   // wave_shr:1
   if (lane > pos) {
     ls = us;
     lj = uj;
@@ -132,34 +138,74 @@ __device__ __forceinline__ void list_insert(float& ls, int& lj, float s, int j, 
   }
 }
 
-// Filter one 128-wide score row against the list and insert what passes.
-__device__ __forceinline__ void row_update(float& ls, int& lj, float v0, float v1, int64_t j0,
-                                           int kc, uint64_t kmask) {
+// Compare-exchange with the lane at distance jj; the lower lane keeps the smaller key
+// when `asc`, the larger otherwise.
+__device__ __forceinline__ void cmpx(float& s, int& j, int jj, bool asc) {
+  const int lane = lane_id();
+  const float so = __shfl_xor(s, jj, WAVE);
+  const int jo = __shfl_xor(j, jj, WAVE);
+  const bool lower = (lane & jj) == 0;
+  if ((lower == asc) ? key_less(so, jo, s, j) : key_less(s, j, so, jo)) {
+    s = so;
+    j = jo;
+  }
+}
+
+// Bitonic sort of one value per lane, ascending by (score, index).
+__device__ __forceinline__ void wave_sort64(float& s, int& j) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int kk = 2; kk <= 64; kk <<= 1)
+#pragma unroll
+    for (int jj = kk >> 1; jj > 0; jj >>= 1) cmpx(s, j, jj, (lane & kk) == 0);
+}
+
+// The 64 smallest of two ascending wave lists, ascending, into (ls, lj).
+__device__ __forceinline__ void wave_merge64(float& ls, int& lj, float bs, int bj) {
+  const int lane = lane_id();
+  const float rs = __shfl(bs, 63 - lane, WAVE);   // reversed: [list asc | b desc] is bitonic
+  const int rj = __shfl(bj, 63 - lane, WAVE);
+  if (key_less(rs, rj, ls, lj)) {
+    ls = rs;
+    lj = rj;
+  }
+#pragma unroll
+  for (int jj = 32; jj > 0; jj >>= 1) cmpx(ls, lj, jj, true);
+}
+
+// Filter 64 candidates (one per lane) against the row list and take in what passes.
+__device__ __forceinline__ void half_update(float& ls, int& lj, float v, int jv, int kc) {
   float th = rdlane(ls, kc - 1);
-  uint64_t m0 = __ballot(v0 < th), m1 = __ballot(v1 < th);
-  while (m0 | m1) {
-    float sv;
-    int jv;
-    if (m0) {
-      const int src = __ffsll((unsigned long long)m0) - 1;
-      m0 &= m0 - 1;
-      sv = rdlane(v0, src);
-      jv = (int)(j0 + src);
-    } else {
-      const int src = __ffsll((unsigned long long)m1) - 1;
-      m1 &= m1 - 1;
-      sv = rdlane(v1, src);
-      jv = (int)(j0 + 64 + src);
+  uint64_t msk = __ballot(v < th);
+  if (!msk) return;
+  if (__popcll(msk) <= 6) {
+    while (msk) {
+      const int src = __ffsll((unsigned long long)msk) - 1;
+      msk &= msk - 1;
+      const float sv = rdlane(v, src);
+      if (sv < th) {
+        list_insert(ls, lj, sv, __builtin_amdgcn_readlane(jv, src));
+        th = rdlane(ls, kc - 1);
+      }
     }
-    if (sv < th) {
-      list_insert(ls, lj, sv, jv, kmask);
-      th = rdlane(ls, kc - 1);
-    }
+  } else {
+    float bs = v < th ? v : INFINITY;
+    int bj = v < th ? jv : INT_MAX;
+    wave_sort64(bs, bj);
+    wave_merge64(ls, lj, bs, bj);
   }
 }
 
 // ------------------------------------------------------------------------------------
 // GEMM + top-K'.  PREC 0: fp32 MFMA 32x32x2, BK = 16; PREC 1: bf16 MFMA 16x16x32, BK = 64.
+//
+// Work is the grid of (query tile, database tile) pairs, P = QT * NT, in query-major
+// order.  Workgroup L takes the contiguous range [L*P/G, (L+1)*P/G): every workgroup
+// does the same amount of MFMA work, a query tile is cut into at most a few
+// segments (each refills its lists once), and because G >= QT a range touches at
+// most two query tiles.  Workgroups are dispatched round-robin over the 8 XCDs, so
+// the logical id is remapped to give each XCD a block of consecutive ranges: its
+// workgroups then share query tiles in their own L2.
 // ------------------------------------------------------------------------------------
 template <int PREC>
 struct GemmCfg;
@@ -167,15 +213,13 @@ template <>
 struct GemmCfg<0> {
   static constexpr int BK = 16;                 // columns per stage
   static constexpr int ALD = BK + 4;            // staging row stride (elements)
-  static constexpr int ESZ = 4;
-  static constexpr size_t STAGE_B = (size_t)2 * (KBQ + KBN) * ALD * ESZ;
+  static constexpr size_t STAGE_B = (size_t)2 * (KBQ + KBN) * ALD * 4;
 };
 template <>
 struct GemmCfg<1> {
   static constexpr int BK = 64;
   static constexpr int ALD = BK + 8;
-  static constexpr int ESZ = 2;
-  static constexpr size_t STAGE_B = (size_t)2 * (KBQ + KBN) * ALD * ESZ;
+  static constexpr size_t STAGE_B = (size_t)2 * (KBQ + KBN) * ALD * 2;
 };
 
 template <int PREC>
@@ -184,264 +228,290 @@ constexpr size_t gemm_lds_bytes() {
                                                          : (size_t)KBQ * SLD * 4;
 }
 
+// Workgroup holding tile pair t under the range schedule (floor((t+1)G - 1)/P).
+__host__ __device__ __forceinline__ int64_t range_owner(int64_t t, int64_t G, int64_t P) {
+  return ((t + 1) * G - 1) / P;
+}
+
+// Scores s[i][j] = ||y_j||^2 - 2 x_i . y_j of one 128 x 128 tile into Ss (LDS).
+// 8 waves as 2 (query rows) x 4 (db columns); wave tile 64 x 32.
 template <int PREC>
-__global__ __launch_bounds__(KNT) void knn_gemm_topk_kernel(
-    const void* __restrict__ xsrc, int64_t mp, const float* __restrict__ norms, int64_t n, int kc,
-    int tiles_per_split, int include_self, float* __restrict__ cand_s, int* __restrict__ cand_j) {
+__device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64_t mp,
+                                            const float* __restrict__ norms, int64_t n, int64_t q0,
+                                            int64_t j0, int include_self, unsigned char* smem) {
   using G = GemmCfg<PREC>;
+  const int tid = threadIdx.x;
+  const int w = tid / WAVE, lane = tid % WAVE;
+  const int wr = w / 4, wc = w % 4;      // wave tile: rows 64*wr.., cols 32*wc..
+  float* Ss = reinterpret_cast<float*>(smem);
+  const int nch = (int)(mp / G::BK);
+  if constexpr (PREC == 0) {
+    const float* xs = reinterpret_cast<const float*>(xsrc);
+    float* As = reinterpret_cast<float*>(smem);
+    floatx16 acc[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][r] = 0.0f;
+    // staging: 128 query rows + 128 db rows, 16 floats each = 1024 float4; 2 per thread
+    float4 pre[2];
+    auto gload = [&](int ch) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int f = tid + u * KNT;
+        const int row = f / 4;           // 0..255: queries then db rows
+        const int c4 = f % 4;
+        const int64_t g = row < KBQ ? q0 + row : j0 + (row - KBQ);
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (g < n) v = *reinterpret_cast<const float4*>(xs + g * mp + (int64_t)ch * G::BK + 4 * c4);
+        pre[u] = v;
+      }
+    };
+    auto sstore = [&](int buf) {
+      float* base = As + (size_t)buf * (KBQ + KBN) * G::ALD;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int f = tid + u * KNT;
+        *reinterpret_cast<float4*>(base + (f / 4) * G::ALD + 4 * (f % 4)) = pre[u];
+      }
+    };
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+      if (ch + 1 < nch) gload(ch + 1);
+      const float* base = As + (size_t)(ch & 1) * (KBQ + KBN) * G::ALD;
+      const int h = lane / 32;
+      float av[2][8], bv[8];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const float* pa = base + (64 * wr + 32 * a + lane % 32) * G::ALD + 8 * h;
+        const float4 x0 = *reinterpret_cast<const float4*>(pa);
+        const float4 x1 = *reinterpret_cast<const float4*>(pa + 4);
+        av[a][0] = x0.x; av[a][1] = x0.y; av[a][2] = x0.z; av[a][3] = x0.w;
+        av[a][4] = x1.x; av[a][5] = x1.y; av[a][6] = x1.z; av[a][7] = x1.w;
+      }
+      {
+        const float* pb = base + (KBQ + 32 * wc + lane % 32) * G::ALD + 8 * h;
+        const float4 y0 = *reinterpret_cast<const float4*>(pb);
+        const float4 y1 = *reinterpret_cast<const float4*>(pb + 4);
+        bv[0] = y0.x; bv[1] = y0.y; bv[2] = y0.z; bv[3] = y0.w;
+        bv[4] = y1.x; bv[5] = y1.y; bv[6] = y1.z; bv[7] = y1.w;
+      }
+      // k order inside a stage: lane half h supplies column 8h+s at step s, for A and B alike
+#pragma unroll
+      for (int st = 0; st < 8; ++st)
+#pragma unroll
+        for (int a = 0; a < 2; ++a) acc[a] = mfma32x32x2(av[a][st], bv[st], acc[a]);
+      if (ch + 1 < nch) sstore((ch + 1) & 1);
+      __syncthreads();
+    }
+    const int col = 32 * wc + lane % 32;
+    const int64_t gj = j0 + col;
+    const float nj = gj < n ? norms[gj] : 0.0f;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 64 * wr + 32 * a + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
+        float sc = fmaf(-2.0f, acc[a][r], nj);
+        if (gj >= n || (!include_self && gj == q0 + row)) sc = INFINITY;
+        Ss[row * SLD + col] = sc;
+      }
+  } else {
+    const uint16_t* xs = reinterpret_cast<const uint16_t*>(xsrc);
+    uint16_t* As = reinterpret_cast<uint16_t*>(smem);
+    floatx4 acc[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // staging: 256 rows x 64 bf16 = 2048 chunks of 16 B; 4 per thread
+    uint4 pre[4];
+    auto gload = [&](int ch) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int f = tid + u * KNT;
+        const int row = f / 8;
+        const int c8 = f % 8;
+        const int64_t g = row < KBQ ? q0 + row : j0 + (row - KBQ);
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (g < n) v = *reinterpret_cast<const uint4*>(xs + g * mp + (int64_t)ch * G::BK + 8 * c8);
+        pre[u] = v;
+      }
+    };
+    auto sstore = [&](int buf) {
+      uint16_t* base = As + (size_t)buf * (KBQ + KBN) * G::ALD;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int f = tid + u * KNT;
+        *reinterpret_cast<uint4*>(base + (f / 8) * G::ALD + 8 * (f % 8)) = pre[u];
+      }
+    };
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+      if (ch + 1 < nch) gload(ch + 1);
+      const uint16_t* base = As + (size_t)(ch & 1) * (KBQ + KBN) * G::ALD;
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk) {           // two 32-wide k steps per stage
+        shortx8 av[4], bv[2];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+          av[a] = *reinterpret_cast<const shortx8*>(
+              base + (64 * wr + 16 * a + lane % 16) * G::ALD + 32 * kk + 8 * (lane / 16));
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          bv[b] = *reinterpret_cast<const shortx8*>(
+              base + (KBQ + 32 * wc + 16 * b + lane % 16) * G::ALD + 32 * kk + 8 * (lane / 16));
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) acc[a][b] = mfma16x16x32bf16(av[a], bv[b], acc[a][b]);
+      }
+      if (ch + 1 < nch) sstore((ch + 1) & 1);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int col = 32 * wc + 16 * b + lane % 16;
+      const int64_t gj = j0 + col;
+      const float nj = gj < n ? norms[gj] : 0.0f;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 64 * wr + 16 * a + 4 * (lane / 16) + r;
+          float sc = fmaf(-2.0f, acc[a][b][r], nj);
+          if (gj >= n || (!include_self && gj == q0 + row)) sc = INFINITY;
+          Ss[row * SLD + col] = sc;
+        }
+    }
+  }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) void knn_gemm_topk_kernel(
+    const void* __restrict__ xsrc, int64_t mp, const float* __restrict__ norms, int64_t n, int kc,
+    int64_t G, int smax, int include_self, float* __restrict__ cand_s, int* __restrict__ cand_j) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
   const int w = tid / WAVE, lane = tid % WAVE;
-  const int64_t q0 = (int64_t)blockIdx.x * KBQ;
-  const int split = blockIdx.y;
-  const int64_t ntiles = (n + KBN - 1) / KBN;
-  const int64_t t_begin = (int64_t)split * tiles_per_split;
-  const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
-  const uint64_t kmask = kc >= 64 ? ~0ull : ((1ull << kc) - 1ull);
+  const int64_t QT = (n + KBQ - 1) / KBQ;
+  const int64_t NT = (n + KBN - 1) / KBN;
+  const int64_t P = QT * NT;
+  // XCD-aware logical id: dispatch order bid -> XCD bid % 8
+  const int64_t bid = blockIdx.x;
+  const int64_t L = (G % 8 == 0) ? (bid % 8) * (G / 8) + bid / 8 : bid;
+  const int64_t tb = (L * P) / G, te = ((L + 1) * P) / G;
+  const float* Ss = reinterpret_cast<const float*>(smem);
 
-  float ls[32];
-  int lj[32];
+  float ls[RPW];
+  int lj[RPW];
+  int64_t cur_qt = -1;
+  auto flush = [&]() {
+    if (cur_qt < 0) return;
+    const int64_t seg = L - range_owner(cur_qt * NT, G, P);
 #pragma unroll
-  for (int r = 0; r < 32; ++r) {
-    ls[r] = INFINITY;
-    lj[r] = INT_MAX;
-  }
-
-  const int wr = w / 2, wc = w % 2;      // wave tile: rows 64*wr.., cols 64*wc..
-  float* Ss = reinterpret_cast<float*>(smem);
-  const int nch = (int)(mp / G::BK);
-
-  for (int64_t t = t_begin; t < t_end; ++t) {
-    const int64_t j0 = t * KBN;
-    if constexpr (PREC == 0) {
-      const float* xs = reinterpret_cast<const float*>(xsrc);
-      float* As = reinterpret_cast<float*>(smem);
-      floatx16 acc[2][2];
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-          for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
-      // staging: 128 query rows + 128 db rows, 16 floats each = 1024 float4; 4 per thread
-      float4 pre[4];
-      auto gload = [&](int ch) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int f = tid + u * KNT;
-          const int row = (f / 4) % 128;
-          const int c4 = f % 4;
-          const bool isq = f < 512;
-          const int64_t g = isq ? q0 + row : j0 + row;
-          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (g < n) v = *reinterpret_cast<const float4*>(xs + g * mp + (int64_t)ch * G::BK + 4 * c4);
-          pre[u] = v;
-        }
-      };
-      auto sstore = [&](int buf) {
-        float* base = As + (size_t)buf * (KBQ + KBN) * G::ALD;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int f = tid + u * KNT;
-          const int row = f / 4;         // 0..255: queries then db rows
-          const int c4 = f % 4;
-          *reinterpret_cast<float4*>(base + row * G::ALD + 4 * c4) = pre[u];
-        }
-      };
-      gload(0);
-      sstore(0);
-      __syncthreads();
-      for (int ch = 0; ch < nch; ++ch) {
-        if (ch + 1 < nch) gload(ch + 1);
-        const float* base = As + (size_t)(ch & 1) * (KBQ + KBN) * G::ALD;
-        const int h = lane / 32;
-        float av[2][8], bv[2][8];
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const float* pa = base + (64 * wr + 32 * a + lane % 32) * G::ALD + 8 * h;
-          const float4 x0 = *reinterpret_cast<const float4*>(pa);
-          const float4 x1 = *reinterpret_cast<const float4*>(pa + 4);
-          av[a][0] = x0.x; av[a][1] = x0.y; av[a][2] = x0.z; av[a][3] = x0.w;
-          av[a][4] = x1.x; av[a][5] = x1.y; av[a][6] = x1.z; av[a][7] = x1.w;
-          const float* pb = base + (KBQ + 64 * wc + 32 * a + lane % 32) * G::ALD + 8 * h;
-          const float4 y0 = *reinterpret_cast<const float4*>(pb);
-          const float4 y1 = *reinterpret_cast<const float4*>(pb + 4);
-          bv[a][0] = y0.x; bv[a][1] = y0.y; bv[a][2] = y0.z; bv[a][3] = y0.w;
-          bv[a][4] = y1.x; bv[a][5] = y1.y; bv[a][6] = y1.z; bv[a][7] = y1.w;
-        }
-#pragma unroll
-        for (int s = 0; s < 8; ++s)
-#pragma unroll
-          for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b) acc[a][b] = mfma32x32x2(av[a][s], bv[b][s], acc[a][b]);
-        if (ch + 1 < nch) sstore((ch + 1) & 1);
-        __syncthreads();
+    for (int rr = 0; rr < RPW; ++rr) {
+      const int64_t gi = cur_qt * KBQ + RPW * w + rr;
+      if (gi < n && lane < kc) {
+        const int64_t o = ((cur_qt * smax + seg) * KBQ + RPW * w + rr) * kc + lane;
+        cand_s[o] = ls[rr];
+        cand_j[o] = lj[rr];
       }
-      // scores to LDS: D[i][j] with i = query row, j = db column
+    }
+  };
+  for (int64_t t = tb; t < te; ++t) {
+    const int64_t qt = t / NT, dt = t % NT;
+    if (qt != cur_qt) {
+      flush();
+      cur_qt = qt;
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          const int col = 64 * wc + 32 * b + lane % 32;
-          const int64_t gj = j0 + col;
-          const float nj = gj < n ? norms[gj] : 0.0f;
-#pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int row = 64 * wr + 32 * a + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
-            const int64_t gi = q0 + row;
-            float sc = fmaf(-2.0f, acc[a][b][r], nj);
-            if (gj >= n || (!include_self && gj == gi)) sc = INFINITY;
-            Ss[row * SLD + col] = sc;
-          }
-        }
-    } else {
-      const uint16_t* xs = reinterpret_cast<const uint16_t*>(xsrc);
-      uint16_t* As = reinterpret_cast<uint16_t*>(smem);
-      // 4 waves as 2 x 2, each 64 x 64 = 4 x 4 blocks of 16 x 16
-      floatx4 acc[4][4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
-      // staging: 256 rows x 64 bf16 = 256 x 8 chunks of 16 B = 2048; 8 per thread
-      uint4 pre[8];
-      auto gload = [&](int ch) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int f = tid + u * KNT;
-          const int row = f / 8;
-          const int c8 = f % 8;
-          const bool isq = row < 128;
-          const int64_t g = isq ? q0 + row : j0 + (row - 128);
-          uint4 v = make_uint4(0u, 0u, 0u, 0u);
-          if (g < n) v = *reinterpret_cast<const uint4*>(xs + g * mp + (int64_t)ch * G::BK + 8 * c8);
-          pre[u] = v;
-        }
-      };
-      auto sstore = [&](int buf) {
-        uint16_t* base = As + (size_t)buf * (KBQ + KBN) * G::ALD;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int f = tid + u * KNT;
-          const int row = f / 8;
-          const int c8 = f % 8;
-          *reinterpret_cast<uint4*>(base + row * G::ALD + 8 * c8) = pre[u];
-        }
-      };
-      gload(0);
-      sstore(0);
-      __syncthreads();
-      for (int ch = 0; ch < nch; ++ch) {
-        if (ch + 1 < nch) gload(ch + 1);
-        const uint16_t* base = As + (size_t)(ch & 1) * (KBQ + KBN) * G::ALD;
-#pragma unroll
-        for (int kk = 0; kk < 2; ++kk) {           // two 32-wide k steps per stage
-          shortx8 av[4], bv[4];
-#pragma unroll
-          for (int a = 0; a < 4; ++a) {
-            const uint16_t* pa = base + (64 * wr + 16 * a + lane % 16) * G::ALD + 32 * kk + 8 * (lane / 16);
-            av[a] = *reinterpret_cast<const shortx8*>(pa);
-            const uint16_t* pb = base + (KBQ + 64 * wc + 16 * a + lane % 16) * G::ALD + 32 * kk + 8 * (lane / 16);
-            bv[a] = *reinterpret_cast<const shortx8*>(pb);
-          }
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = mfma16x16x32bf16(av[a], bv[b], acc[a][b]);
-        }
-        if (ch + 1 < nch) sstore((ch + 1) & 1);
-        __syncthreads();
+      for (int rr = 0; rr < RPW; ++rr) {
+        ls[rr] = INFINITY;
+        lj[rr] = INT_MAX;
       }
+    }
+    const int64_t j0 = dt * KBN;
+    tile_scores<PREC>(xsrc, mp, norms, n, qt * KBQ, j0, include_self, smem);
+    __syncthreads();
+    // top-K' update: wave w owns query rows RPW*w .. RPW*w+RPW-1 of the tile.  A cheap,
+    // unrolled filter marks the rows with any score below their threshold; only those
+    // rows are then swapped into working registers and updated (one copy of the code).
+    uint32_t need = 0;
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+    for (int rr = 0; rr < RPW; ++rr) {
+      const int row = RPW * w + rr;
+      const float th = rdlane(ls[rr], kc - 1);
+      const bool hit = (Ss[row * SLD + lane] < th) || (Ss[row * SLD + 64 + lane] < th);
+      need |= (__ballot(hit) != 0ull ? 1u : 0u) << rr;
+    }
+    while (need) {
+      const int rr = __ffs(need) - 1;
+      need &= need - 1;
+      float ws = ls[0];
+      int wj = lj[0];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int col = 64 * wc + 16 * b + lane % 16;
-          const int64_t gj = j0 + col;
-          const float nj = gj < n ? norms[gj] : 0.0f;
+      for (int r = 1; r < RPW; ++r)
+        if (rr == r) {
+          ws = ls[r];
+          wj = lj[r];
+        }
+      const int row = RPW * w + rr;
+#pragma nounroll
+      for (int h = 0; h < 2; ++h)
+        half_update(ws, wj, Ss[row * SLD + 64 * h + lane], (int)(j0 + 64 * h + lane), kc);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = 64 * wr + 16 * a + 4 * (lane / 16) + r;
-            const int64_t gi = q0 + row;
-            float sc = fmaf(-2.0f, acc[a][b][r], nj);
-            if (gj >= n || (!include_self && gj == gi)) sc = INFINITY;
-            Ss[row * SLD + col] = sc;
-          }
+      for (int r = 0; r < RPW; ++r)
+        if (rr == r) {
+          ls[r] = ws;
+          lj[r] = wj;
         }
     }
     __syncthreads();
-    // top-K' update: wave w owns query rows 32w .. 32w+31
-#pragma unroll
-    for (int rr = 0; rr < 32; ++rr) {
-      const int row = 32 * w + rr;
-      const float v0 = Ss[row * SLD + lane];
-      const float v1 = Ss[row * SLD + 64 + lane];
-      row_update(ls[rr], lj[rr], v0, v1, j0, kc, kmask);
-    }
-    __syncthreads();
   }
-  // write this split's lists
-#pragma unroll
-  for (int rr = 0; rr < 32; ++rr) {
-    const int64_t gi = q0 + 32 * w + rr;
-    if (gi < n && lane < kc) {
-      const int64_t o = ((int64_t)split * n + gi) * kc + lane;
-      cand_s[o] = ls[rr];
-      cand_j[o] = lj[rr];
-    }
-  }
+  flush();
 }
 
 // ------------------------------------------------------------------------------------
 // merge + float32 re-rank + certificate.  One wave per query, 4 queries per block.
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void knn_rerank_kernel(
-    const float* __restrict__ X, int64_t n, int64_t m, int64_t ldx, int k, int kc, int splits,
-    const float* __restrict__ cand_s, const int* __restrict__ cand_j, const float* __restrict__ norms,
-    const float* __restrict__ radius, const float* __restrict__ stats, int precision,
-    int include_self, int32_t* __restrict__ idx_out, float* __restrict__ d2_out,
-    uint8_t* __restrict__ kflags) {
-  __shared__ float sh_s[4][4 * KCMAX];
-  __shared__ int sh_j[4][4 * KCMAX];
-  __shared__ float sel_s[4][KCMAX];
-  __shared__ int sel_j[4][KCMAX];
+    const float* __restrict__ X, int64_t n, int64_t m, int64_t ldx, int k, int kc, int64_t G,
+    int smax, const float* __restrict__ cand_s, const int* __restrict__ cand_j,
+    const float* __restrict__ norms, const float* __restrict__ radius,
+    const float* __restrict__ stats, int include_self, int32_t* __restrict__ idx_out,
+    float* __restrict__ d2_out, uint8_t* __restrict__ kflags) {
   const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-  const int64_t qraw = (int64_t)blockIdx.x * 4 + wv;
-  const bool valid = qraw < n;
-  const int64_t qi = valid ? qraw : n - 1;   // tail waves mirror the last query, write nothing
-  const int tot = splits * kc;
-  // gather the split lists
-  for (int t = lane; t < tot; t += WAVE) {
-    const int sp = t / kc, r = t % kc;
-    const int64_t o = ((int64_t)sp * n + qi) * kc + r;
-    sh_s[wv][t] = cand_s[o];
-    sh_j[wv][t] = cand_j[o];
-  }
-  __syncthreads();
-  // rank every gathered candidate by (score, index, slot); keep rank < kc
-  for (int t = lane; t < tot; t += WAVE) {
-    const float s = sh_s[wv][t];
-    const int j = sh_j[wv][t];
-    int rk = 0;
-    for (int u = 0; u < tot; ++u) {
-      const float su = sh_s[wv][u];
-      const int ju = sh_j[wv][u];
-      rk += (su < s) || (su == s && (ju < j || (ju == j && u < t)));
+  const int64_t qi = (int64_t)blockIdx.x * 4 + wv;
+  if (qi >= n) return;                      // whole wave exits together
+  const int64_t QT = (n + KBQ - 1) / KBQ;
+  const int64_t NT = (n + KBN - 1) / KBN;
+  const int64_t P = QT * NT;
+  const int64_t qt = qi / KBQ, row = qi % KBQ;
+  const int64_t nseg = range_owner(qt * NT + NT - 1, G, P) - range_owner(qt * NT, G, P) + 1;
+  // merge the segment lists (each ascending) into the 64 best
+  float ls = INFINITY;
+  int lj = INT_MAX;
+  for (int64_t sg = 0; sg < nseg; ++sg) {
+    const int64_t o = ((qt * smax + sg) * KBQ + row) * kc;
+    float bs = INFINITY;
+    int bj = INT_MAX;
+    if (lane < kc) {
+      bs = cand_s[o + lane];
+      bj = cand_j[o + lane];
     }
-    if (rk < kc) {
-      sel_s[wv][rk] = s;
-      sel_j[wv][rk] = j;
-    }
+    wave_merge64(ls, lj, bs, bj);
   }
-  __syncthreads();
-  const float s_last = sel_s[wv][kc - 1];   // worst kept GEMM score
-  // exact float32 difference-form distances of the kc candidates
+  const float s_last = rdlane(ls, kc - 1);   // every non-candidate scores >= s_last
+  // exact float32 difference-form distances of the kc candidates (lane r <- candidate r)
   float myd = INFINITY;
   int myj = INT_MAX;
   const float* xq = X + qi * ldx;
   for (int r = 0; r < kc; ++r) {
-    const int j = sel_j[wv][r];
+    const int j = __builtin_amdgcn_readlane(lj, r);
     float d = INFINITY;
     if (j >= 0 && (int64_t)j < n) {
       const float* xj = X + (int64_t)j * ldx;
@@ -457,29 +527,21 @@ __global__ __launch_bounds__(256) void knn_rerank_kernel(
       myj = (j >= 0 && (int64_t)j < n) ? j : INT_MAX;
     }
   }
-  // the point itself (MC_INCLUDE_SELF) always comes first
-  float key = myd;
-  if (include_self && myj == (int)qi) key = -1.0f;
-  // rank by (distance, index)
-  int rk = 0;
-  for (int u = 0; u < kc; ++u) {
-    const float ku = __shfl(key, u, WAVE);
-    const int ju = __shfl(myj, u, WAVE);
-    rk += (ku < key) || (ku == key && ju < myj);
+  // order by (distance, index); the point itself (MC_INCLUDE_SELF) comes first
+  float key = lane < kc ? myd : INFINITY;
+  int kj = lane < kc ? myj : INT_MAX;
+  if (include_self && kj == (int)qi) key = -1.0f;
+  wave_sort64(key, kj);
+  // after the sort, lane r holds rank r; recover its distance
+  float dr = key;
+  if (include_self && kj == (int)qi) dr = 0.0f;
+  if (lane < k) {
+    idx_out[qi * k + lane] = kj;
+    if (d2_out) d2_out[qi * k + lane] = dr;
   }
-  if (valid && lane < kc && rk < k) {
-    idx_out[qi * k + rk] = myj;
-    if (d2_out) d2_out[qi * k + rk] = myd;
-  }
-  // k-th and (k+1)-th distances
-  float dk = 0.0f, dk1 = INFINITY;
-  {
-    const uint64_t bk = __ballot(lane < kc && rk == k - 1);
-    const uint64_t bk1 = __ballot(lane < kc && rk == k);
-    if (bk) dk = rdlane(myd, __ffsll((unsigned long long)bk) - 1);
-    if (bk1) dk1 = rdlane(myd, __ffsll((unsigned long long)bk1) - 1);
-  }
-  if (valid && lane == 0 && kflags) {
+  const float dk = rdlane(dr, k - 1);
+  const float dk1 = kc > k ? rdlane(dr, k) : INFINITY;
+  if (lane == 0 && kflags) {
     uint8_t fl = 0;
     const double u = 0x1p-24;
     const double gam = (double)(m + 2) * u / (1.0 - (double)(m + 2) * u);
@@ -488,14 +550,13 @@ __global__ __launch_bounds__(256) void knn_rerank_kernel(
     // certificate: every non-candidate y has GEMM score >= s_last; bound its true distance
     // from below and compare with the k-th re-ranked distance.
     bool cert = true;
-    if (tot < n - (include_self ? 0 : 1) && isfinite(s_last)) {
+    if ((int64_t)kc < n - (include_self ? 0 : 1) && isfinite(s_last)) {
       const double ni = (double)norms[qi], rn = sqrt(ni);
       const double nmax = (double)stats[0], emax = (double)stats[1], ei = (double)radius[qi];
       const double gm = (double)(m + 8) * u / (1.0 - (double)(m + 8) * u);
-      // |gemm d2 - ||xc_i - xc_j||^2| <= E (dot rounding of the low-precision copy + fp32 sums)
-      double E = 2.0 * (ei * (nmax + emax) + rn * emax) + 2.0 * gm * (rn + ei) * (nmax + emax) +
-                 4.0 * u * (ni + nmax * nmax) + gm * (ni + nmax * nmax);
-      (void)precision;
+      // |gemm d2 - ||xc_i - xc_j||^2|: rounding of the low-precision copy, fp32 dot and norms
+      const double E = 2.0 * (ei * (nmax + emax) + rn * emax) + 2.0 * gm * (rn + ei) * (nmax + emax) +
+                       4.0 * u * (ni + nmax * nmax) + gm * (ni + nmax * nmax);
       const double lo2 = ni + (double)s_last - E;
       // centring rounding: | ||xc_i - xc_j|| - ||x_i - x_j|| | <= u (||xc_i|| + ||xc_j||) (1+u)
       const double lo = (lo2 > 0.0 ? sqrt(lo2) : 0.0) - 1.0001 * u * (rn + nmax);
@@ -515,15 +576,16 @@ static int64_t knn_mp(int64_t m, int precision) {
   return ((m + bk - 1) / bk) * bk;
 }
 
-static int knn_splits(int64_t n, int kc) {
-  const int64_t qt = (n + KBQ - 1) / KBQ;
-  const int64_t nt = (n + KBN - 1) / KBN;
-  int64_t s = (1024 + qt - 1) / qt;   // aim for >= 1024 workgroups (4 per CU)
-  if (s > 16) s = 16;
-  if (s > (4 * KCMAX) / kc) s = (4 * KCMAX) / kc;   // merged lists must fit the re-rank LDS
-  if (s > nt) s = nt;
-  if (s < 1) s = 1;
-  return (int)s;
+// Workgroups of the GEMM stage: about 2 per CU (register and LDS bound), never fewer
+// than the query tiles (so a range spans at most two), a multiple of 8 for the XCD map.
+static int64_t knn_groups(int64_t n) {
+  const int64_t QT = (n + KBQ - 1) / KBQ, NT = (n + KBN - 1) / KBN, P = QT * NT;
+  int64_t G = 512;
+  if (G < QT) G = QT;
+  if (G > P) G = P;
+  if (G >= 8) G = (G + 7) / 8 * 8;
+  if (G > P) G = P;
+  return G;
 }
 
 KnnPlan knn_plan(int64_t n, int64_t m, int k, int kc, int precision) {
@@ -533,7 +595,18 @@ KnnPlan knn_plan(int64_t n, int64_t m, int k, int kc, int precision) {
   p.k = k;
   p.kc = kc;
   p.precision = precision;
-  p.splits = knn_splits(n, kc);
+  const int64_t QT = (n + KBQ - 1) / KBQ;
+  p.groups = knn_groups(n);
+  {
+    // most workgroups sharing one query tile under the range schedule
+    const int64_t NT = (n + KBN - 1) / KBN, P = QT * NT;
+    int64_t smax = 1;
+    for (int64_t qt = 0; qt < QT; ++qt) {
+      const int64_t c = range_owner(qt * NT + NT - 1, p.groups, P) - range_owner(qt * NT, p.groups, P) + 1;
+      if (c > smax) smax = c;
+    }
+    p.smax = (int)smax;
+  }
   const int64_t mp = knn_mp(m, precision);
   const int64_t parts = 64;
   size_t off = 0;
@@ -541,8 +614,9 @@ KnnPlan knn_plan(int64_t n, int64_t m, int k, int kc, int precision) {
   p.off_norm = off;   off += align256((size_t)n * 4);
   p.off_colsum = off; off += align256((size_t)parts * m * 8 + (size_t)m * 4);
   p.off_stats = off;  off += align256((size_t)n * 4 + 64);
-  p.off_cand_s = off; off += align256((size_t)p.splits * n * kc * 4);
-  p.off_cand_j = off; off += align256((size_t)p.splits * n * kc * 4);
+  const size_t cand = (size_t)QT * p.smax * KBQ * kc * 4;
+  p.off_cand_s = off; off += align256(cand);
+  p.off_cand_j = off; off += align256(cand);
   p.off_xlow = off;   off += precision == 1 ? align256((size_t)n * mp * 2) : 0;
   p.off_scale = off;
   p.total = off;
@@ -584,10 +658,6 @@ hipError_t launch_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int k, 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
 
-  const int64_t nt = (n + KBN - 1) / KBN;
-  const int splits = plan.splits;
-  const int tps = (int)((nt + splits - 1) / splits);
-  const dim3 grid((unsigned)((n + KBQ - 1) / KBQ), (unsigned)splits);
   static bool attr_set = false;   // LDS beyond 64 KiB needs the opt-in attribute
   if (!attr_set) {
     hipFuncSetAttribute(reinterpret_cast<const void*>(&knn_gemm_topk_kernel<0>),
@@ -597,20 +667,23 @@ hipError_t launch_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int k, 
     (void)hipGetLastError();
     attr_set = true;
   }
+  const dim3 grid((unsigned)plan.groups);
   timing_begin(4, stream);
   if (precision == 0) {
     hipLaunchKernelGGL(knn_gemm_topk_kernel<0>, grid, dim3(KNT), gemm_lds_bytes<0>(), stream,
-                       (const void*)xc, mp, norms, n, kc, tps, include_self ? 1 : 0, cand_s, cand_j);
+                       (const void*)xc, mp, norms, n, kc, plan.groups, plan.smax,
+                       include_self ? 1 : 0, cand_s, cand_j);
   } else {
     hipLaunchKernelGGL(knn_gemm_topk_kernel<1>, grid, dim3(KNT), gemm_lds_bytes<1>(), stream,
-                       (const void*)xb, mp, norms, n, kc, tps, include_self ? 1 : 0, cand_s, cand_j);
+                       (const void*)xb, mp, norms, n, kc, plan.groups, plan.smax,
+                       include_self ? 1 : 0, cand_s, cand_j);
   }
   timing_end(4, stream);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   timing_begin(5, stream);
   hipLaunchKernelGGL(knn_rerank_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream, X, n, m,
-                     ldx, k, kc, splits, cand_s, cand_j, norms, radius, stats, precision,
+                     ldx, k, kc, plan.groups, plan.smax, cand_s, cand_j, norms, radius, stats,
                      include_self ? 1 : 0, idx, d2, kflags);
   timing_end(5, stream);
   return hipGetLastError();

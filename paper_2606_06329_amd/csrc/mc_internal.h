@@ -20,7 +20,8 @@ struct KnnPlan {
   int64_t n, m;
   int k, kc;          // neighbours, candidates kept per query (rerank_factor * k)
   int precision;
-  int splits;         // database splits of the GEMM/top-k stage
+  int64_t groups;     // workgroups of the GEMM/top-k stage
+  int smax;           // list segments reserved per query tile
   size_t off_xc, off_norm, off_colsum, off_stats, off_cand_s, off_cand_j, off_xlow, off_scale, total;
 };
 

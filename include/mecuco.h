@@ -148,6 +148,8 @@ int mc_curvature_fast(const float* X, int64_t n, int64_t m, int64_t ldx, const i
  * m > rank, and this ABI fixes it so results are reproducible.
  *
  * Arguments as mc_curvature_fast without `variant`; precision MC_FP32 only.
+ * V_r (float64) and the centred patch are held on chip: m * (8 (k-1) + 4 k) bytes
+ * must stay within about 150 KiB (e.g. m <= 1230 at k = 11), else MC_ESHAPE.
  */
 int mc_curvature_exact(const float* X, int64_t n, int64_t m, int64_t ldx, const int32_t* idx,
                        int32_t k, int32_t precision, uint32_t flags, float* kappa_out,
@@ -161,7 +163,10 @@ int mc_curvature_exact(const float* X, int64_t n, int64_t m, int64_t ldx, const 
  * gap_eps = 0 gives the exact derivative.
  *
  *   grad_kappa   [n] float32, device
- *   grad_X       [n x ldx] float32, device, ACCUMULATED into (atomic adds)
+ *   grad_X       [n x ldx] float32, device, ACCUMULATED into (atomic adds, so the
+ *                summation order, and the last bits, vary from run to run)
+ *   k            2 <= k <= 16 (MC_ESHAPE above)
+ * Points whose patch is degenerate (tau = 0) or non-finite contribute nothing.
  */
 int mc_curvature_backward(const float* X, int64_t n, int64_t m, int64_t ldx, const int32_t* idx,
                           int32_t k, int32_t variant, const float* grad_kappa, float gap_eps,

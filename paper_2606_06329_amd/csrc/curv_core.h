@@ -1,0 +1,481 @@
+// Shared front half of the per-point curvature kernels (gfx950): patch gather and
+// centring, the moment GEMM on MFMA, the k x k Jacobi eigen-solve and the range
+// basis Ut = U_p diag(sigma_p^{-1/2}).  Used by the Fast forward and its adjoint.
+//
+// Moments of the centred patch X_c (k x m), one MFMA GEMM over the m columns:
+//   [X_c ; q ; 1] (k+2 x m)  times  [X_c[a] o X_c[b] (a<=b) | 1] (m x k(k+1)/2+1)
+// gives, in `mom` (row-major, stride NPAD):
+//   row j < k : T[j][pair(a,b)] = sum_c X_c[j,c] X_c[a,c] X_c[b,c],  T[j][np] = r_j = sum_c X_c[j,c]
+//   row k     : Q[pair(a,b)]    = sum_c q_c X_c[a,c] X_c[b,c],  q_c = sum_j X_c[j,c]^2
+//   row k+1   : K[pair(a,b)]    = sum_c X_c[a,c] X_c[b,c]
+// tau * (k-1) = ||X_c||_F^2 is accumulated separately in float64.
+#pragma once
+
+#include <math.h>
+
+#include "mc_device.h"
+
+namespace mc {
+
+constexpr int FCH = 64;        // patch columns per staged chunk
+constexpr int FLDX = FCH + 1;  // LDS row stride (floats) of a staged chunk
+constexpr int JAC_MAX_SWEEPS = 40;
+
+template <int KMAX, int NW_, int PPW_, size_t EXTRA_B = 0>
+struct CurvCfg {
+  static constexpr int KM = KMAX;
+  static constexpr int MB = (KMAX + 2 + 15) / 16;           // 16-row blocks of the LHS
+  static constexpr int ROWS = (16 * MB > KMAX + 3) ? 16 * MB : KMAX + 3;
+  static constexpr int NPC = KMAX * (KMAX + 1) / 2 + 1;     // pair columns + ones column
+  static constexpr int NB = (NPC + 15) / 16;                // 16-column blocks of the RHS
+  static constexpr int NW = NW_;                            // waves per point
+  static constexpr int PPW = PPW_;                          // points per workgroup
+  static constexpr int NTG = NW * WAVE;                     // threads per point
+  static constexpr int NT = PPW * NTG;                      // threads per workgroup
+  static constexpr int NBW = (NB + NW - 1) / NW;            // RHS blocks per wave
+  static constexpr int KK = (KMAX + 1) & ~1;                // even Jacobi size
+  static constexpr int JLD = KK + 1;                        // Jacobi row stride (doubles)
+  static constexpr int NPAD = NB * 16;
+  // LDS layout of one point (bytes); the staged chunk and the moments share storage.
+  static constexpr size_t LHS_B = (size_t)ROWS * FLDX * 4;
+  static constexpr size_t MOM_B = (size_t)(KMAX + 2) * NPAD * 4;
+  static constexpr size_t U0_B = LHS_B > MOM_B ? LHS_B : MOM_B;
+  static constexpr size_t OFF_JA = (U0_B + 15) & ~(size_t)15;
+  static constexpr size_t OFF_JV = OFF_JA + (size_t)KK * JLD * 8;
+  static constexpr size_t OFF_UT = OFF_JV + (size_t)KK * JLD * 8;
+  static constexpr size_t OFF_Y = OFF_UT + (size_t)KMAX * KMAX * 8;
+  static constexpr size_t OFF_RED = OFF_Y + (size_t)KMAX * KMAX * 8;     // 16 doubles x NW
+  static constexpr size_t OFF_ROT = OFF_RED + (size_t)16 * NW * 8;        // c, s per pair
+  static constexpr size_t OFF_INT = OFF_ROT + (size_t)KK * 8;
+  static constexpr size_t N_INT = KMAX + KK + 8;                          // nb, ord, misc
+  static constexpr size_t OFF_PIDX = OFF_INT + N_INT * 4;
+  static constexpr size_t OFF_PJ = OFF_PIDX + (size_t)KMAX * KMAX * 2;
+  static constexpr size_t OFF_EXTRA = (OFF_PJ + 2 * NPAD + 15) & ~(size_t)15;
+  static constexpr size_t BYTES = (OFF_EXTRA + EXTRA_B + 15) & ~(size_t)15;
+};
+
+// Index of pair (a, b), a <= b, in row-major upper-triangular order of a k x k matrix.
+__device__ __forceinline__ int pair_index(int a, int b, int k) {
+  if (a > b) { int t = a; a = b; b = t; }
+  return a * k - (a * (a - 1)) / 2 + (b - a);
+}
+
+// Synchronise the threads of one point: a single wave needs only an LDS fence.
+template <int NW>
+__device__ __forceinline__ void gsync() {
+  if constexpr (NW == 1) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// Sum of NV doubles over the threads of one point; result valid in every thread.
+template <int NW, int NV>
+__device__ __forceinline__ void group_sum(double (&v)[NV], double* red, int tg) {
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  if constexpr (NW > 1) {
+    const int w = tg / WAVE, l = tg % WAVE;
+    __syncthreads();
+    if (l == 0) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) red[w * 16 + i] = v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double s = 0.0;
+      for (int ww = 0; ww < NW; ++ww) s += red[ww * 16 + i];
+      v[i] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// Lane `lane` of the staging wave holds column c0+lane of the k gathered rows in xr.
+template <int KMAX>
+__device__ __forceinline__ void load_chunk(float (&xr)[KMAX], const float* __restrict__ X,
+                                           int64_t ldx, const int* nb, int k, int64_t m,
+                                           int64_t c0, int lane) {
+  const int64_t c = c0 + lane;
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) {
+    float v = 0.0f;
+    if (j < k && c < m) v = X[(int64_t)nb[j] * ldx + c];
+    xr[j] = v;
+  }
+}
+
+// Centre one column of the patch in float32: the mean is taken of the offsets from the
+// first row, so equal rows give exactly zero and large coordinates cause no cancellation.
+// On return xr[j] holds X_c[j, c].
+template <int KMAX>
+__device__ __forceinline__ void centre_column(float (&xr)[KMAX], int k) {
+#pragma unroll
+  for (int j = KMAX - 1; j >= 0; --j)
+    if (j < k) xr[j] -= xr[0];
+  float s = 0.0f;
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j)
+    if (j < k) s += xr[j];
+  const float mean = s / (float)k;
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j)
+    if (j < k) xr[j] -= mean;
+}
+
+// Player at round-robin position `pos` in round r of the circle schedule on KK players.
+__device__ __forceinline__ int rr_player(int pos, int r, int KK) {
+  if (pos == 0) return 0;
+  int t = pos - 1 + r;
+  if (t >= KK - 1) t -= KK - 1;
+  return t + 1;
+}
+
+// Pointers into one point's LDS region.
+struct PointLds {
+  float* lhs;
+  float* mom;
+  double* JA;
+  double* JV;
+  double* UT;
+  double* YB;
+  double* RED;
+  double* ROT;
+  int* nb;
+  int* ord;
+  int* misc;
+  uint16_t* PIDX;
+  unsigned char* pj1;
+  unsigned char* pj2;
+  unsigned char* extra;
+};
+
+template <class C>
+__device__ __forceinline__ PointLds point_lds(unsigned char* smem) {
+  PointLds P;
+  P.lhs = reinterpret_cast<float*>(smem);
+  P.mom = reinterpret_cast<float*>(smem);
+  P.JA = reinterpret_cast<double*>(smem + C::OFF_JA);
+  P.JV = reinterpret_cast<double*>(smem + C::OFF_JV);
+  P.UT = reinterpret_cast<double*>(smem + C::OFF_UT);
+  P.YB = reinterpret_cast<double*>(smem + C::OFF_Y);
+  P.RED = reinterpret_cast<double*>(smem + C::OFF_RED);
+  P.ROT = reinterpret_cast<double*>(smem + C::OFF_ROT);
+  int* IN = reinterpret_cast<int*>(smem + C::OFF_INT);
+  P.nb = IN;
+  P.ord = IN + C::KM;
+  P.misc = P.ord + C::KK;
+  P.PIDX = reinterpret_cast<uint16_t*>(smem + C::OFF_PIDX);
+  P.pj1 = smem + C::OFF_PJ;
+  P.pj2 = P.pj1 + C::NPAD;
+  P.extra = smem + C::OFF_EXTRA;
+  return P;
+}
+
+// Front half for point i: setup, moments, Jacobi, eigen order, numerical rank and Ut.
+// Returns 0 on success, or PF_NONFINITE (bad index or non-finite patch value).
+// Outputs (valid in every thread of the group): tauk = ||X_c||^2, sig0 = sigma_1,
+// pe = numerical rank, sweep = Jacobi sweeps used.
+template <int KMAX, class C, int PREC = 0>
+__device__ uint8_t patch_front(const PointLds& P, const float* __restrict__ X, int64_t n, int64_t m,
+                               int64_t ldx, const int32_t* __restrict__ idx, int k, int64_t i,
+                               int tg, double& tauk, double& sig0, int& pe, int& sweep) {
+  const int w = tg / WAVE;
+  const int lane = tg % WAVE;
+  float* lhs = P.lhs;
+  float* mom = P.mom;
+  double* JA = P.JA;
+  double* JV = P.JV;
+  int* misc = P.misc;
+  int* nb = P.nb;
+  const int np = k * (k + 1) / 2;
+  const int npc = np + 1;
+  const int nbr = (npc + 15) / 16;    // RHS blocks in use
+
+  // ---- setup: neighbour rows, pair tables, zero rows --------------------------------
+  if (tg < 8) misc[tg] = 0;
+  gsync<C::NW>();
+  if (tg < k) {
+    int v = idx[i * k + tg];
+    if (v < 0 || (int64_t)v >= n) { misc[0] = 1; v = 0; }
+    nb[tg] = v;
+  }
+  for (int t = tg; t < C::NPAD; t += C::NTG) {
+    int a = k + 2, b = k + 2;          // zero row
+    if (t < np) {
+      int r = t;
+      a = 0;
+      while (r >= k - a) { r -= k - a; ++a; }
+      b = a + r;
+    } else if (t == np) {
+      a = b = k + 1;                   // ones row: the column of ones
+    }
+    P.pj1[t] = (unsigned char)a;
+    P.pj2[t] = (unsigned char)b;
+  }
+  for (int t = tg; t < k * k; t += C::NTG)
+    P.PIDX[(t / k) * KMAX + t % k] = (uint16_t)pair_index(t / k, t % k, k);
+  for (int t = tg; t < (C::ROWS - (k + 2)) * FLDX; t += C::NTG) lhs[(k + 2) * FLDX + t] = 0.0f;
+  gsync<C::NW>();
+  if (misc[0]) return PF_NONFINITE;
+
+  // ---- pass over the patch: moments on MFMA --------------------------------------
+  floatx4 acc[C::MB][C::NBW];
+#pragma unroll
+  for (int a = 0; a < C::MB; ++a)
+#pragma unroll
+    for (int b = 0; b < C::NBW; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  int off1[C::NBW], off2[C::NBW];
+#pragma unroll
+  for (int b = 0; b < C::NBW; ++b) {
+    const int nbg = w + C::NW * b;
+    const int pi = nbg * 16 + (lane % 16);
+    const int pc = pi < C::NPAD ? pi : C::NPAD - 1;
+    off1[b] = P.pj1[pc] * FLDX;
+    off2[b] = P.pj2[pc] * FLDX;
+  }
+
+  // bf16 path: K = X_c X_c^T stays float32 (it feeds the eigen-solve and the rank test);
+  // KB x KB blocks of 16 x 16 on v_mfma_f32_16x16x4f32, fed by the same staged values.
+  constexpr int KB = (KMAX + 15) / 16;
+  floatx4 kacc[KB][KB];
+#pragma unroll
+  for (int a = 0; a < KB; ++a)
+#pragma unroll
+    for (int b = 0; b < KB; ++b) kacc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  float xr[KMAX];
+  double tau64 = 0.0;
+  bool nonfinite = false;
+  if (w == 0) load_chunk<KMAX>(xr, X, ldx, nb, k, m, 0, lane);
+
+  for (int64_t c0 = 0; c0 < m; c0 += FCH) {
+    if (w == 0) {
+#pragma unroll
+      for (int j = 0; j < KMAX; ++j)
+        if (j < k) nonfinite |= !isfinite(xr[j]);
+      centre_column<KMAX>(xr, k);
+      float q = 0.0f;
+#pragma unroll
+      for (int j = 0; j < KMAX; ++j) {
+        if (j < k) {
+          const float xc = xr[j];
+          q = fmaf(xc, xc, q);
+          tau64 = fma((double)xc, (double)xc, tau64);
+          lhs[j * FLDX + lane] = xc;
+        }
+      }
+      lhs[k * FLDX + lane] = q;
+      lhs[(k + 1) * FLDX + lane] = (c0 + lane < m) ? 1.0f : 0.0f;
+    }
+    gsync<C::NW>();
+    if (w == 0 && c0 + FCH < m) load_chunk<KMAX>(xr, X, ldx, nb, k, m, c0 + FCH, lane);
+
+    const int64_t rem = m - c0;
+    if constexpr (PREC == 0) {
+      const int steps = rem >= FCH ? FCH / 4 : (int)((rem + 3) / 4);
+      for (int s = 0; s < steps; ++s) {
+        const int col = 4 * s + lane / 16;
+        float av[C::MB];
+#pragma unroll
+        for (int a = 0; a < C::MB; ++a) av[a] = lhs[(16 * a + lane % 16) * FLDX + col];
+#pragma unroll
+        for (int b = 0; b < C::NBW; ++b) {
+          if (w + C::NW * b < nbr) {
+            const float bv = lhs[off1[b] + col] * lhs[off2[b] + col];
+#pragma unroll
+            for (int a = 0; a < C::MB; ++a) acc[a][b] = mfma16x16x4(av[a], bv, acc[a][b]);
+          }
+        }
+      }
+    } else {
+      // 32-column steps; lane l supplies columns 32 s + 8 (l / 16) + e, e = 0..7
+      const int steps = rem >= FCH ? FCH / 32 : (int)((rem + 31) / 32);
+      for (int s = 0; s < steps; ++s) {
+        const int col0 = 32 * s + 8 * (lane / 16);
+        float xa[C::MB][8];
+        shortx8 abf[C::MB];
+#pragma unroll
+        for (int a = 0; a < C::MB; ++a)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            xa[a][e] = lhs[(16 * a + lane % 16) * FLDX + col0 + e];
+            abf[a][e] = (short)f2bf(xa[a][e]);
+          }
+        if (w == 0) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+#pragma unroll
+            for (int a = 0; a < KB; ++a)
+#pragma unroll
+              for (int b = 0; b < KB; ++b) kacc[a][b] = mfma16x16x4(xa[a][e], xa[b][e], kacc[a][b]);
+        }
+#pragma unroll
+        for (int b = 0; b < C::NBW; ++b) {
+          if (w + C::NW * b < nbr) {
+            shortx8 bbf;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) bbf[e] = (short)f2bf(lhs[off1[b] + col0 + e] * lhs[off2[b] + col0 + e]);
+#pragma unroll
+            for (int a = 0; a < C::MB; ++a) acc[a][b] = mfma16x16x32bf16(abf[a], bbf, acc[a][b]);
+          }
+        }
+      }
+    }
+    gsync<C::NW>();
+  }
+
+  // ---- moments to LDS ------------------------------------------------------------
+  if (w == 0) {
+    tau64 = wave_sum(tau64);
+    const int nf = __any(nonfinite);
+    if (lane == 0) {
+      P.RED[15 * C::NW] = tau64;
+      misc[1] = nf;
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < C::NBW; ++b) {
+    const int nbg = w + C::NW * b;
+    if (nbg < nbr) {
+      const int col = nbg * 16 + lane % 16;
+#pragma unroll
+      for (int a = 0; a < C::MB; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * a + 4 * (lane / 16) + r;
+          if (row < (PREC == 0 ? k + 2 : k + 1) && col < npc) mom[row * C::NPAD + col] = acc[a][b][r];
+        }
+    }
+  }
+  if constexpr (PREC != 0) {
+    if (w == 0) {
+#pragma unroll
+      for (int a = 0; a < KB; ++a)
+#pragma unroll
+        for (int b = 0; b < KB; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int x = 16 * a + 4 * (lane / 16) + r, y = 16 * b + lane % 16;
+            if (x <= y && y < k) mom[(k + 1) * C::NPAD + P.PIDX[x * KMAX + y]] = kacc[a][b][r];
+          }
+    }
+  }
+  gsync<C::NW>();
+  tauk = P.RED[15 * C::NW];
+  if (misc[1]) return PF_NONFINITE;
+
+  // ---- k x k eigen-solve: cyclic Jacobi, parallel (round-robin) order, float64 -------
+  // Each round rotates KK/2 disjoint planes.  The update works on 2 x 2 blocks of A
+  // (pair i x pair i') and on row x of V restricted to one pair, so every thread
+  // reads and writes the same cells and the update runs in place.
+  const int KK = (k + 1) & ~1;
+  const int HP = KK / 2;
+  const float* Krow = mom + (k + 1) * C::NPAD;
+  double trace = 0.0;
+  for (int e = tg; e < KK * KK; e += C::NTG) {
+    const int x = e / KK, y = e % KK;
+    JA[x * C::JLD + y] = (x < k && y < k) ? (double)Krow[P.PIDX[x * KMAX + y]] : 0.0;
+    JV[x * C::JLD + y] = (x == y) ? 1.0 : 0.0;
+  }
+  for (int x = 0; x < k; ++x) trace += (double)Krow[P.PIDX[x * KMAX + x]];
+  gsync<C::NW>();
+  const double floor_abs = trace * 0x1p-100;
+  sweep = 0;
+  for (; sweep < JAC_MAX_SWEEPS; ++sweep) {
+    if (tg == 0) misc[2] = 0;
+    for (int r = 0; r < KK - 1; ++r) {
+      if (tg < HP) {
+        const int pa = rr_player(tg, r, KK), pb = rr_player(KK - 1 - tg, r, KK);
+        const int p = pa < pb ? pa : pb, q = pa < pb ? pb : pa;
+        const double app = JA[p * C::JLD + p], aqq = JA[q * C::JLD + q], apq = JA[p * C::JLD + q];
+        double c = 1.0, s = 0.0;
+        const double thr = fmax(0x1p-52 * sqrt(fabs(app) * fabs(aqq)), floor_abs);
+        if (fabs(apq) > thr) {
+          const double theta = (aqq - app) / (2.0 * apq);
+          const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = t * c;
+          misc[2] = 1;
+        }
+        P.ROT[tg] = c;
+        P.ROT[C::KK / 2 + tg] = s;
+      }
+      gsync<C::NW>();
+      // A <- J^T A J on 2 x 2 blocks; V <- V J on row pairs
+      for (int u = tg; u < HP * HP + KK * HP; u += C::NTG) {
+        if (u < HP * HP) {
+          const int bi = u / HP, bj = u % HP;
+          const int pa = rr_player(bi, r, KK), pb = rr_player(KK - 1 - bi, r, KK);
+          const int p = pa < pb ? pa : pb, q = pa < pb ? pb : pa;
+          const int qa = rr_player(bj, r, KK), qb = rr_player(KK - 1 - bj, r, KK);
+          const int p2 = qa < qb ? qa : qb, q2 = qa < qb ? qb : qa;
+          const double c = P.ROT[bi], s = P.ROT[C::KK / 2 + bi];
+          const double c2 = P.ROT[bj], s2 = P.ROT[C::KK / 2 + bj];
+          const double a00 = JA[p * C::JLD + p2], a01 = JA[p * C::JLD + q2];
+          const double a10 = JA[q * C::JLD + p2], a11 = JA[q * C::JLD + q2];
+          // columns: (p2, q2) <- (c2 a_p2 - s2 a_q2, s2 a_p2 + c2 a_q2)
+          const double m00 = c2 * a00 - s2 * a01, m01 = s2 * a00 + c2 * a01;
+          const double m10 = c2 * a10 - s2 * a11, m11 = s2 * a10 + c2 * a11;
+          // rows: (p, q) <- (c m_p - s m_q, s m_p + c m_q)
+          double n00 = c * m00 - s * m10, n01 = c * m01 - s * m11;
+          double n10 = s * m00 + c * m10, n11 = s * m01 + c * m11;
+          if (bi == bj && s != 0.0) {
+            n01 = 0.0;
+            n10 = 0.0;
+          }
+          JA[p * C::JLD + p2] = n00;
+          JA[p * C::JLD + q2] = n01;
+          JA[q * C::JLD + p2] = n10;
+          JA[q * C::JLD + q2] = n11;
+        } else {
+          const int v = u - HP * HP;
+          const int x = v / HP, bj = v % HP;
+          const int qa = rr_player(bj, r, KK), qb = rr_player(KK - 1 - bj, r, KK);
+          const int p2 = qa < qb ? qa : qb, q2 = qa < qb ? qb : qa;
+          const double c2 = P.ROT[bj], s2 = P.ROT[C::KK / 2 + bj];
+          const double v0 = JV[x * C::JLD + p2], v1 = JV[x * C::JLD + q2];
+          JV[x * C::JLD + p2] = c2 * v0 - s2 * v1;
+          JV[x * C::JLD + q2] = s2 * v0 + c2 * v1;
+        }
+      }
+      gsync<C::NW>();
+    }
+    const int any = misc[2];
+    gsync<C::NW>();
+    if (!any) break;
+  }
+
+  // ---- eigen order, numerical rank, Ut = U_p / sqrt(sigma) -------------------------------
+  if (tg < KK) {
+    const double dx = JA[tg * C::JLD + tg];
+    int rk = 0;
+    for (int y = 0; y < KK; ++y) {
+      const double dy = JA[y * C::JLD + y];
+      rk += (dy > dx) || (dy == dx && y < tg);
+    }
+    P.ord[rk] = tg;
+  }
+  gsync<C::NW>();
+  sig0 = JA[P.ord[0] * C::JLD + P.ord[0]];
+  const int plim = (int)((int64_t)(k - 1) < m ? (int64_t)(k - 1) : m);
+  const double rtol = (double)(m > k ? m : k) * 0x1p-24;
+  pe = 0;
+  if (sig0 > 0.0) {
+    while (pe < plim && JA[P.ord[pe] * C::JLD + P.ord[pe]] > rtol * sig0) ++pe;
+  }
+  for (int e = tg; e < k * pe; e += C::NTG) {
+    const int a = e / pe, l = e % pe;
+    const int x = P.ord[l];
+    P.UT[a * KMAX + l] = JV[a * C::JLD + x] / sqrt(JA[x * C::JLD + x]);
+  }
+  gsync<C::NW>();
+  return 0;
+}
+
+}  // namespace mc

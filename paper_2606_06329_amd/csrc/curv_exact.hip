@@ -1,0 +1,259 @@
+// Exact-mode curvature (Theorem 1, eq. kappa_final) with a canonical null basis (gfx950).
+//
+// kappa = |1/2 v^T (C o C) 1 + 1/2 sum v| with C = W^T (W o W), W = [V_r | Q_null] and
+// v = (lambda_r, 0, ..., 0).  Splitting the columns of W into the range and the null
+// space (eq. split) gives kappa = |(t_range + t_null^W)/2 + tau/2| with
+//   t_range  = ||X_c V_r^{o2}||_F^2 / (k-1)
+//   t_null^W = sum_{l >= p} ||X_c (w_l o w_l)||^2 / (k-1),
+// because sum_s lambda_s v_s v_s^T = X_c^T X_c/(k-1).  The paper's Exact branch takes
+// the null columns from an m x m eigensolver, which makes kappa depend on that solver
+// whenever m > rank.  Here Q_null is fixed: the trailing m - p columns of the Householder
+// QR of V_r in LAPACK's convention (dlarfg: beta = -sign(alpha) ||x||, tau = (beta -
+// alpha)/beta), held in compact WY form Q = I - Y T Y^T, so w_l = e_l - Y T y_l with y_l
+// row l of Y.  Cost O((k + p) m^2) per point instead of the eigensolver's O(m^3).
+//
+// One workgroup (4 waves) per point.  V_r (float64) and the centred patch (float32)
+// live in LDS, which bounds m * (8 p + 4 k) (checked on the host).
+#include "curv_core.h"
+#include "mc_internal.h"
+
+namespace mc {
+
+constexpr size_t EXACT_LDS_MAX = 150 * 1024;   // bytes for V_r + patch + T on top of the core
+
+template <int KMAX>
+struct ExactCfgSel {
+  using C = CurvCfg<KMAX, 4, 1, 0>;
+};
+
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  const double s = red[0] + red[1] + red[2] + red[3];
+  __syncthreads();
+  return s;
+}
+
+template <int KMAX>
+__global__ __launch_bounds__(256) void curv_exact_kernel(
+    const float* __restrict__ X, int64_t n, int64_t m, int64_t ldx, const int32_t* __restrict__ idx,
+    int k, float* __restrict__ kappa_out, uint8_t* __restrict__ flags_out) {
+  using C = typename ExactCfgSel<KMAX>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tg = threadIdx.x;
+  const int64_t i = blockIdx.x;
+  const PointLds P = point_lds<C>(smem);
+  double tauk, sig0;
+  int pe, sweep;
+  const uint8_t bad = patch_front<KMAX, C>(P, X, n, m, ldx, idx, k, i, tg, tauk, sig0, pe, sweep);
+  if (bad) {
+    if (tg == 0) {
+      kappa_out[i] = __builtin_nanf("");
+      if (flags_out) flags_out[i] = bad;
+    }
+    return;
+  }
+  const int plim = (int)((int64_t)(k - 1) < m ? (int64_t)(k - 1) : m);
+  uint8_t fl = 0;
+  if (pe < plim) fl |= PF_RANK_DEFICIENT;
+  if (sweep >= JAC_MAX_SWEEPS) fl |= PF_JACOBI_MAXSWEEPS;
+  if (!(sig0 > 0.0) || tauk == 0.0 || pe == 0) {
+    if (tg == 0) {
+      kappa_out[i] = 0.0f;
+      if (flags_out) flags_out[i] = fl | PF_DEGENERATE;
+    }
+    return;
+  }
+  // exact-mode buffers after the core region
+  double* Vd = reinterpret_cast<double*>(smem + C::BYTES);                 // m x pe, row-major
+  float* Xs = reinterpret_cast<float*>(smem + C::BYTES + (size_t)m * pe * 8);   // k x m
+  double* Tf = reinterpret_cast<double*>(smem + C::BYTES + (size_t)m * pe * 8 + (((size_t)k * m * 4 + 15) & ~(size_t)15));
+  double* tau_h = Tf + KMAX * KMAX;                                        // reflector scalars
+  double* red = tau_h + KMAX;                                              // 4 doubles
+  double* wv = red + 8;                                                    // KMAX doubles
+
+  // ---- centred patch into LDS (same float32 centring as the moment pass) --------------------
+  for (int64_t c0 = (int64_t)(tg / WAVE) * WAVE; c0 < m; c0 += 256) {
+    float xr[KMAX];
+    load_chunk<KMAX>(xr, X, ldx, P.nb, k, m, c0, tg % WAVE);
+    centre_column<KMAX>(xr, k);
+    const int64_t c = c0 + tg % WAVE;
+    if (c < m) {
+#pragma unroll
+      for (int j = 0; j < KMAX; ++j)
+        if (j < k) Xs[(int64_t)j * m + c] = xr[j];
+    }
+  }
+  __syncthreads();
+  // ---- V_r = X_c^T Ut (float64), and t_range = ||X_c V_r^{o2}||^2 ------------------------
+  for (int64_t e = tg; e < m * pe; e += 256) {
+    const int64_t a = e / pe;
+    const int l = (int)(e % pe);
+    double s = 0.0;
+    for (int j = 0; j < k; ++j) s = fma((double)Xs[(int64_t)j * m + a], P.UT[j * KMAX + l], s);
+    Vd[a * pe + l] = s;
+  }
+  __syncthreads();
+  double trange = 0.0;
+  for (int e = tg; e < k * pe; e += 256) {
+    const int j = e / pe, l = e % pe;
+    double s = 0.0;
+    for (int64_t a = 0; a < m; ++a) {
+      const double v = Vd[a * pe + l];
+      s = fma((double)Xs[(int64_t)j * m + a], v * v, s);
+    }
+    trange = fma(s, s, trange);
+  }
+  trange = block_sum256(trange, red);
+
+  // ---- Householder QR of V_r in place (LAPACK geqr2 / dlarfg convention) --------------------
+  for (int j = 0; j < pe; ++j) {
+    double ss = 0.0;
+    for (int64_t a = j + 1 + tg; a < m; a += 256) ss = fma(Vd[a * pe + j], Vd[a * pe + j], ss);
+    const double xnorm2 = block_sum256(ss, red);
+    const double alpha = Vd[(int64_t)j * pe + j];
+    double tauj = 0.0, scal = 0.0, beta = alpha;
+    if (xnorm2 > 0.0) {
+      const double nrm = sqrt(alpha * alpha + xnorm2);
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      tauj = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    __syncthreads();
+    if (tauj != 0.0) {
+      for (int64_t a = j + 1 + tg; a < m; a += 256) Vd[a * pe + j] *= scal;   // v below the diagonal
+    }
+    if (tg == 0) {
+      Vd[(int64_t)j * pe + j] = beta;
+      tau_h[j] = tauj;
+    }
+    __syncthreads();
+    // apply H_j = I - tau v v^T (v_j = 1) to columns j+1 .. pe-1
+    for (int c = j + 1; c < pe; ++c) {
+      double d = 0.0;
+      for (int64_t a = j + 1 + tg; a < m; a += 256) d = fma(Vd[a * pe + j], Vd[a * pe + c], d);
+      d = block_sum256(d, red) + Vd[(int64_t)j * pe + c];
+      const double f = tauj * d;
+      if (tg == 0) Vd[(int64_t)j * pe + c] -= f;
+      for (int64_t a = j + 1 + tg; a < m; a += 256) Vd[a * pe + c] -= f * Vd[a * pe + j];
+      __syncthreads();
+    }
+  }
+  // ---- compact WY factor T (LAPACK dlarft, forward, columnwise) -----------------------------
+  // Y[:, j] = (0..0, 1, Vd[j+1:, j]);  T[j][j] = tau_j;  T[0:j, j] = -tau_j T[0:j, 0:j] (Y^T y_j)[0:j]
+  for (int j = 0; j < pe; ++j) {
+    for (int s = 0; s < j; ++s) {
+      // (Y^T y_j)[s] = sum_a Y[a][s] Y[a][j] = Y[j][s] + sum_{a>j} Y[a][s] Y[a][j]
+      double d = 0.0;
+      for (int64_t a = j + 1 + tg; a < m; a += 256) d = fma(Vd[a * pe + s], Vd[a * pe + j], d);
+      d = block_sum256(d, red) + Vd[(int64_t)j * pe + s];
+      if (tg == 0) wv[s] = -tau_h[j] * d;
+    }
+    __syncthreads();
+    if (tg < j) {
+      double t = 0.0;
+      for (int s = tg; s < j; ++s) t = fma(Tf[tg * KMAX + s], wv[s], t);   // T upper triangular
+      Tf[tg * KMAX + j] = t;
+    }
+    if (tg == 0) Tf[j * KMAX + j] = tau_h[j];
+    __syncthreads();
+  }
+  // ---- null columns: w_l = e_l - Y z_l, z_l = T y_l,  t_null^W = sum_l ||X_c (w_l o w_l)||^2 ----------
+  double tnull = 0.0;
+  for (int64_t l = pe + tg; l < m; l += 256) {
+    double z[KMAX];
+#pragma unroll
+    for (int s = 0; s < KMAX; ++s) {
+      double t = 0.0;
+      if (s < pe)
+        for (int u = s; u < pe; ++u) t = fma(Tf[s * KMAX + u], Vd[l * pe + u], t);   // y_l = row l of Y
+      z[s] = t;
+    }
+    double acc[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) acc[j] = 0.0;
+    for (int64_t a = 0; a < m; ++a) {
+      // Y[a][s]: 0 for a < s, 1 for a == s, Vd[a][s] below the diagonal
+      double yz = 0.0;
+#pragma unroll
+      for (int s = 0; s < KMAX; ++s) {
+        if (s < pe) {
+          const double y = a > s ? Vd[a * pe + s] : (a == s ? 1.0 : 0.0);
+          yz = fma(y, z[s], yz);
+        }
+      }
+      const double wa = (a == l ? 1.0 : 0.0) - yz;
+      const double w2 = wa * wa;
+#pragma unroll
+      for (int j = 0; j < KMAX; ++j)
+        if (j < k) acc[j] = fma((double)Xs[(int64_t)j * m + a], w2, acc[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j)
+      if (j < k) tnull = fma(acc[j], acc[j], tnull);
+  }
+  tnull = block_sum256(tnull, red);
+
+  if (tg == 0) {
+    const double km1 = (double)(k - 1);
+    const double kap = fabs(0.5 * (trange / km1 + tnull / km1) + 0.5 * tauk / km1);
+    kappa_out[i] = (float)kap;
+    if (flags_out) flags_out[i] = fl;
+  }
+}
+
+template <int KMAX>
+static size_t exact_lds_bytes(int64_t m, int k) {
+  using C = typename ExactCfgSel<KMAX>::C;
+  const int p = k - 1;
+  return C::BYTES + (size_t)m * p * 8 + (((size_t)k * m * 4 + 15) & ~(size_t)15) +
+         (size_t)(KMAX * KMAX + KMAX + 8 + KMAX) * 8;
+}
+
+static size_t exact_bytes(int64_t m, int k) {
+  if (k <= 4) return exact_lds_bytes<4>(m, k);
+  if (k <= 8) return exact_lds_bytes<8>(m, k);
+  if (k <= 12) return exact_lds_bytes<12>(m, k);
+  if (k <= 16) return exact_lds_bytes<16>(m, k);
+  if (k <= 20) return exact_lds_bytes<20>(m, k);
+  if (k <= 24) return exact_lds_bytes<24>(m, k);
+  if (k <= 28) return exact_lds_bytes<28>(m, k);
+  return exact_lds_bytes<32>(m, k);
+}
+
+bool curv_exact_fits(int64_t m, int k) { return exact_bytes(m, k) <= EXACT_LDS_MAX; }
+
+size_t curv_exact_ws_bytes(int64_t, int64_t, int) { return 256; }
+
+template <int KMAX>
+static hipError_t launch_exact_k(const float* X, int64_t n, int64_t m, int64_t ldx,
+                                 const int32_t* idx, int k, float* kappa, uint8_t* flags,
+                                 hipStream_t stream) {
+  const size_t lds = exact_lds_bytes<KMAX>(m, k);
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&curv_exact_kernel<KMAX>),
+                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipGetLastError();
+  timing_begin(7, stream);
+  hipLaunchKernelGGL(curv_exact_kernel<KMAX>, dim3((unsigned)n), dim3(256), lds, stream, X, n, m, ldx,
+                     idx, k, kappa, flags);
+  timing_end(7, stream);
+  return hipGetLastError();
+}
+
+hipError_t launch_curv_exact(const float* X, int64_t n, int64_t m, int64_t ldx, const int32_t* idx,
+                             int k, float* kappa, uint8_t* flags, void* ws, hipStream_t stream) {
+  (void)ws;
+  if (k <= 4) return launch_exact_k<4>(X, n, m, ldx, idx, k, kappa, flags, stream);
+  if (k <= 8) return launch_exact_k<8>(X, n, m, ldx, idx, k, kappa, flags, stream);
+  if (k <= 12) return launch_exact_k<12>(X, n, m, ldx, idx, k, kappa, flags, stream);
+  if (k <= 16) return launch_exact_k<16>(X, n, m, ldx, idx, k, kappa, flags, stream);
+  if (k <= 20) return launch_exact_k<20>(X, n, m, ldx, idx, k, kappa, flags, stream);
+  if (k <= 24) return launch_exact_k<24>(X, n, m, ldx, idx, k, kappa, flags, stream);
+  if (k <= 28) return launch_exact_k<28>(X, n, m, ldx, idx, k, kappa, flags, stream);
+  return launch_exact_k<32>(X, n, m, ldx, idx, k, kappa, flags, stream);
+}
+
+}  // namespace mc

@@ -149,6 +149,7 @@ int mc_curvature_exact(const float* X, int64_t n, int64_t m, int64_t ldx, const 
     return (precision == MC_BF16 || precision == MC_FP8) ? MC_EPRECISION : MC_EINVAL;
   }
   if (ws_bytes < mc::curv_exact_ws_bytes(n, m, k) || misaligned(ws)) return MC_EWORKSPACE;
+  if (!mc::curv_exact_fits(m, k)) return MC_ESHAPE;
   st = check_device();
   if (st) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -166,6 +167,7 @@ int mc_curvature_backward(const float* X, int64_t n, int64_t m, int64_t ldx, con
   if (!idx || !grad_kappa || !grad_X) return MC_EINVAL;
   if (variant != MC_FAST_PAPER && variant != MC_FAST_HAAR) return MC_EINVAL;
   if (!(gap_eps >= 0.0f) || gap_eps > 1.0f) return MC_EINVAL;
+  if (k > 16) return MC_ESHAPE;   // the adjoint keeps its k x k(k+1)/2 third-moment adjoint in LDS
   (void)ws;
   (void)ws_bytes;
   st = check_device();

@@ -36,6 +36,7 @@ hipError_t launch_curv_exact(const float* X, int64_t n, int64_t m, int64_t ldx, 
                              int k, float* kappa, uint8_t* flags, void* ws, hipStream_t stream);
 
 size_t curv_exact_ws_bytes(int64_t n, int64_t m, int k);
+bool curv_exact_fits(int64_t m, int k);   // patch and V_r fit the exact kernel's LDS
 
 hipError_t launch_curv_backward(const float* X, int64_t n, int64_t m, int64_t ldx,
                                 const int32_t* idx, int k, int variant, const float* gk,

@@ -1,0 +1,68 @@
+"""GPU parity of mc_curvature_exact (Theorem 1 with the canonical Householder null basis)
+against the float64 oracle's canonical exact value."""
+import numpy as np
+import pytest
+
+from oracle import curvature as oc
+from oracle import knn as ok
+from paper_2606_06329_amd import synth
+from tests.gpu_common import TOL_FP32, rel_err, to_dev
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+CASES = [("sphere", 500, 20, 10, 1001), ("swissroll", 600, 128, 12, 4041),
+         ("clusters", 300, 784, 11, 2041), ("torus", 400, 96, 16, 3041), ("swissroll", 300, 9, 5, 4042)]
+
+
+def _separated(Xc, rel=1e-3):
+    """Range singular values pairwise separated (the canonical basis is then unique)."""
+    _, s, _ = np.linalg.svd(Xc, full_matrices=False)
+    s = s[: Xc.shape[0] - 1]
+    return np.all(np.diff(s[::-1] ** 2) > rel * s[0] ** 2)
+
+
+@pytest.mark.parametrize("name,n,m,k,seed", CASES, ids=[f"{c[0]}-{c[1]}x{c[2]}-k{c[3]}" for c in CASES])
+def test_exact_parity(name, n, m, k, seed):
+    import paper_2606_06329_amd as P
+    X = synth.WORKLOADS[name][0](n=n, m=m, seed=seed)
+    idx, _, _, _ = ok.knn(X.astype(np.float64), k)
+    print(f"exact {name} n={n} m={m} k={k}", flush=True)
+    kap, fl = P.curvature_exact(to_dev(X), torch.from_numpy(idx.astype(np.int32)).cuda())
+    kap, fl = kap.cpu().numpy(), fl.cpu().numpy()
+    X64 = X.astype(np.float64)
+    rows = np.arange(0, n, max(1, n // 120))
+    errs, checked = [], 0
+    for i in rows:
+        Xc = oc.patch(X64, idx[i])
+        t = oc.fast_terms(Xc)
+        tau = t["tau"]
+        assert 0.5 * tau * (1 - 1e-5) <= kap[i] <= tau * (1 + 1e-5)      # bracket, every point
+        if fl[i] & 4 or t["p_eff"] != min(k - 1, m) or not _separated(Xc):
+            continue
+        want = oc.canonical_exact_kappa(Xc)
+        errs.append(rel_err(kap[i], want))
+        checked += 1
+    print(f"  checked {checked}, max rel err {max(errs):.2e}")
+    assert checked >= len(rows) // 2
+    assert max(errs) <= TOL_FP32
+
+
+def test_exact_equals_fast_haar_when_q_is_one():
+    """m = k: one null direction, so the Haar reading is the exact value."""
+    import paper_2606_06329_amd as P
+    X = synth.torus(n=400, m=12, seed=3051)
+    idx, _, _, _ = ok.knn(X.astype(np.float64), 12)
+    idd = torch.from_numpy(idx.astype(np.int32)).cuda()
+    ke, _ = P.curvature_exact(to_dev(X), idd)
+    kh, _ = P.curvature_fast(to_dev(X), idd, "haar")
+    assert rel_err(ke.cpu().numpy(), kh.cpu().numpy()).max() <= 1e-4
+
+
+def test_exact_shape_limit():
+    import paper_2606_06329_amd as P
+    from paper_2606_06329_amd._lib import MecucoError
+    X = torch.zeros((100, 4096), device="cuda")
+    idx = torch.zeros((100, 32), dtype=torch.int32, device="cuda")
+    with pytest.raises(MecucoError):
+        P.curvature_exact(X, idx)

@@ -135,3 +135,24 @@ def test_k2_and_m1():
             kap, fl = P.curvature_fast(to_dev(X), to_dev_idx(idx), variant)
             want, _ = oracle_fast(X, idx, variant)
             assert rel_err(kap.cpu().numpy(), want).max() <= TOL_FP32
+
+
+BF16_CASES = [("clusters", 900, 784, 11, 2061), ("torus", 1500, 256, 16, 3061), ("blobs", 500, 1024, 32, 5061),
+              ("swissroll", 800, 128, 12, 4061)]
+
+
+@pytest.mark.parametrize("name,n,m,k,seed", BF16_CASES, ids=[f"{c[0]}-{c[1]}x{c[2]}-k{c[3]}" for c in BF16_CASES])
+@pytest.mark.parametrize("variant", ["paper", "haar"])
+def test_fast_bf16_parity(name, n, m, k, seed, variant):
+    """bf16 moments (float32 accumulation, float32 Gram) against the float64 oracle: 2e-2 bar."""
+    import paper_2606_06329_amd as P
+    from tests.gpu_common import TOL_LOW
+    X, idx = _case(name, n, m, seed, k)
+    kap, fl = P.curvature_fast(to_dev(X), to_dev_idx(idx), variant, "bf16")
+    kap, fl = kap.cpu().numpy(), fl.cpu().numpy()
+    want, pe = oracle_fast(X, idx, variant)
+    okr = ((fl & 4) == 0) & (pe == min(k - 1, m))
+    err = rel_err(kap, want)[okr]
+    print(f"bf16 {name} {variant}: max {err.max():.2e} median {np.median(err):.2e}")
+    assert okr.mean() > 0.95
+    assert err.max() <= TOL_LOW

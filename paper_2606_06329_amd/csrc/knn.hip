@@ -4,16 +4,17 @@
 // Pipeline (all on one stream, workspace owned by the caller):
 //  1. knn_colsum / knn_center: subtract the column mean (distances are
 //     translation invariant; centring shrinks ||x||^2 and with it the
-//     cancellation in ||x||^2 + ||y||^2 - 2 x.y), write the centred copy with a
-//     zero-padded row stride, float32 norms, a per-row rounding radius for the
-//     candidate certificate, and a bf16 copy when asked.
+//     cancellation in ||x||^2 + ||y||^2 - 2 x.y) and write the centred copy in
+//     the GEMM's input format (float32, bf16, or fp8 e4m3 with per-row scales)
+//     with a zero-padded row stride, float32 norms, and a per-row rounding
+//     radius of the low-precision copy for the candidate certificate.
 //  2. knn_gemm_topk: query tile x database tile scores s = ||y||^2 - 2 x.y on
-//     MFMA (fp32 32x32x2 or bf16 16x16x32), written to LDS, then each wave keeps
-//     a sorted list of the K' best (score, index) per query row in registers
-//     (lane r holds rank r); candidates are filtered against the K'-th score
-//     with a ballot and inserted with a wave-wide shift.  The database range is
-//     split over blockIdx.y so that the grid fills the chip.
-//  3. knn_rerank: merge the split lists, recompute the K' distances in float32
+//     MFMA (fp32 32x32x2, bf16 16x16x32 or fp8 16x16x32), written to LDS; each
+//     wave keeps a sorted 64-entry list of (score, index) per query row across
+//     its lanes, filters every row against its K'-th entry with a ballot and
+//     takes in survivors by a DPP shift (few) or a bitonic sort and merge (many).
+//     The tile-pair grid is cut into equal contiguous ranges, one per workgroup.
+//  3. knn_rerank: merge the range segments, recompute the K' distances in float32
 //     difference form sum_a (x_a - y_a)^2 from the original X, order by
 //     (distance, index), keep k, and flag ambiguous gaps and candidate sets
 //     that cannot be certified complete.
@@ -32,6 +33,7 @@ constexpr int KNT = 512;   // threads per GEMM workgroup (8 waves)
 constexpr int RPW = KBQ / (KNT / 64);   // query rows owned by one wave in the top-k stage
 constexpr int SLD = KBN + 4;  // score-tile row stride (floats)
 constexpr int KCMAX = 64;  // largest candidate list
+constexpr int KPARTS = 256; // row blocks of the column-mean reduction
 
 // ------------------------------------------------------------------------------------
 // prep
@@ -58,25 +60,40 @@ __global__ __launch_bounds__(256) void knn_mean_kernel(const double* __restrict_
   mu[c] = (float)(s / (double)n);
 }
 
-// One wave per row: centred float32 copy (row stride mp, zero padded), bf16 copy
-// (optional), norm ||xc||^2 (float32, from a float64 sum), rounding radius.
+// One wave per row: the centred row xc = fl(x - mu) in the GEMM's input format (float32,
+// bf16, or fp8 e4m3 with the per-row scale s = max|xc| / 448), zero padded to the row
+// stride mp; its norm ||xc||^2 (float32, from a float64 sum); and the rounding radius
+// ||lowp(xc) - xc|| of the low-precision copy (0 on the float32 path).
 __global__ __launch_bounds__(256) void knn_center_kernel(
     const float* __restrict__ X, int64_t n, int64_t m, int64_t ldx, int64_t mp,
-    const float* __restrict__ mu, float* __restrict__ xc, uint16_t* __restrict__ xb,
+    const float* __restrict__ mu, void* __restrict__ xout, float* __restrict__ scales,
     float* __restrict__ norms, float* __restrict__ radius, int precision) {
   const int64_t r = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
   const int lane = threadIdx.x % WAVE;
   if (r >= n) return;
   double s = 0.0, e = 0.0;
-  for (int64_t c = lane; c < mp; c += WAVE) {
-    float v = 0.0f;
-    if (c < m) v = X[r * ldx + c] - mu[c];
-    xc[r * mp + c] = v;
+  float amax = 0.0f;
+  for (int64_t c = lane; c < m; c += WAVE) {
+    const float v = X[r * ldx + c] - mu[c];
     s = fma((double)v, (double)v, s);
-    if (precision == 1) {
+    amax = fmaxf(amax, fabsf(v));
+  }
+  amax = wave_max(amax);
+  const float sc = amax > 0.0f ? amax / 448.0f : 1.0f;
+  const float isc = 1.0f / sc;
+  for (int64_t c = lane; c < mp; c += WAVE) {
+    const float v = c < m ? X[r * ldx + c] - mu[c] : 0.0f;
+    if (precision == 0) {
+      reinterpret_cast<float*>(xout)[r * mp + c] = v;
+    } else if (precision == 1) {
       const uint16_t h = f2bf(v);
-      xb[r * mp + c] = h;
+      reinterpret_cast<uint16_t*>(xout)[r * mp + c] = h;
       const double d = (double)bf2f(h) - (double)v;
+      e = fma(d, d, e);
+    } else {
+      const int pk = __builtin_amdgcn_cvt_pk_fp8_f32(v * isc, 0.0f, 0, false);
+      reinterpret_cast<uint8_t*>(xout)[r * mp + c] = (uint8_t)(pk & 0xff);
+      const double d = (double)sc * (double)__builtin_amdgcn_cvt_f32_fp8(pk, 0) - (double)v;
       e = fma(d, d, e);
     }
   }
@@ -84,7 +101,8 @@ __global__ __launch_bounds__(256) void knn_center_kernel(
   e = wave_sum(e);
   if (lane == 0) {
     norms[r] = (float)s;
-    radius[r] = (float)sqrt(e);    // ||bf16(xc) - xc|| (0 on the fp32 path)
+    radius[r] = (float)(sqrt(e) * (1.0 + 0x1p-20));   // rounded up: it bounds an error
+    if (scales) scales[r] = sc;
   }
 }
 
@@ -221,6 +239,12 @@ struct GemmCfg<1> {
   static constexpr int ALD = BK + 8;
   static constexpr size_t STAGE_B = (size_t)2 * (KBQ + KBN) * ALD * 2;
 };
+template <>
+struct GemmCfg<2> {
+  static constexpr int BK = 128;                // fp8 bytes per row per stage
+  static constexpr int ALD = BK + 16;
+  static constexpr size_t STAGE_B = (size_t)2 * (KBQ + KBN) * ALD;
+};
 
 template <int PREC>
 constexpr size_t gemm_lds_bytes() {
@@ -237,7 +261,8 @@ __host__ __device__ __forceinline__ int64_t range_owner(int64_t t, int64_t G, in
 // 8 waves as 2 (query rows) x 4 (db columns); wave tile 64 x 32.
 template <int PREC>
 __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64_t mp,
-                                            const float* __restrict__ norms, int64_t n, int64_t q0,
+                                            const float* __restrict__ norms,
+                                            const float* __restrict__ scales, int64_t n, int64_t q0,
                                             int64_t j0, int include_self, unsigned char* smem) {
   using G = GemmCfg<PREC>;
   const int tid = threadIdx.x;
@@ -318,7 +343,7 @@ __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64
         if (gj >= n || (!include_self && gj == q0 + row)) sc = INFINITY;
         Ss[row * SLD + col] = sc;
       }
-  } else {
+  } else if constexpr (PREC == 1) {
     const uint16_t* xs = reinterpret_cast<const uint16_t*>(xsrc);
     uint16_t* As = reinterpret_cast<uint16_t*>(smem);
     floatx4 acc[4][2];
@@ -388,13 +413,89 @@ __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64
           Ss[row * SLD + col] = sc;
         }
     }
+  } else {
+    // fp8 e4m3 (OCP) with per-row scales: x ~ s_i * x8_i, dot = s_i s_j (x8_i . x8_j)
+    const uint8_t* xs = reinterpret_cast<const uint8_t*>(xsrc);
+    uint8_t* As = reinterpret_cast<uint8_t*>(smem);
+    floatx4 acc[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // staging: 256 rows x 128 bytes = 2048 chunks of 16 B; 4 per thread
+    uint4 pre[4];
+    auto gload = [&](int ch) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int f = tid + u * KNT;
+        const int row = f / 8;
+        const int c16 = f % 8;
+        const int64_t g = row < KBQ ? q0 + row : j0 + (row - KBQ);
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (g < n) v = *reinterpret_cast<const uint4*>(xs + g * mp + (int64_t)ch * G::BK + 16 * c16);
+        pre[u] = v;
+      }
+    };
+    auto sstore = [&](int buf) {
+      uint8_t* base = As + (size_t)buf * (KBQ + KBN) * G::ALD;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int f = tid + u * KNT;
+        *reinterpret_cast<uint4*>(base + (f / 8) * G::ALD + 16 * (f % 8)) = pre[u];
+      }
+    };
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+      if (ch + 1 < nch) gload(ch + 1);
+      const uint8_t* base = As + (size_t)(ch & 1) * (KBQ + KBN) * G::ALD;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {           // four 32-wide k steps per stage
+        long av[4], bv[2];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+          av[a] = *reinterpret_cast<const long*>(
+              base + (64 * wr + 16 * a + lane % 16) * G::ALD + 32 * kk + 8 * (lane / 16));
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          bv[b] = *reinterpret_cast<const long*>(
+              base + (KBQ + 32 * wc + 16 * b + lane % 16) * G::ALD + 32 * kk + 8 * (lane / 16));
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av[a], bv[b], acc[a][b], 0, 0, 0);
+      }
+      if (ch + 1 < nch) sstore((ch + 1) & 1);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int col = 32 * wc + 16 * b + lane % 16;
+      const int64_t gj = j0 + col;
+      const float nj = gj < n ? norms[gj] : 0.0f;
+      const float sj = gj < n ? scales[gj] : 0.0f;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 64 * wr + 16 * a + 4 * (lane / 16) + r;
+          const int64_t gi = q0 + row;
+          const float si = gi < n ? scales[gi] : 0.0f;
+          float sc = fmaf(-2.0f * si * sj, acc[a][b][r], nj);
+          if (gj >= n || (!include_self && gj == gi)) sc = INFINITY;
+          Ss[row * SLD + col] = sc;
+        }
+    }
   }
 }
 
 template <int PREC>
 __global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) void knn_gemm_topk_kernel(
-    const void* __restrict__ xsrc, int64_t mp, const float* __restrict__ norms, int64_t n, int kc,
-    int64_t G, int smax, int include_self, float* __restrict__ cand_s, int* __restrict__ cand_j) {
+    const void* __restrict__ xsrc, int64_t mp, const float* __restrict__ norms,
+    const float* __restrict__ scales, int64_t n, int kc, int64_t G, int smax, int include_self,
+    float* __restrict__ cand_s, int* __restrict__ cand_j) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
   const int w = tid / WAVE, lane = tid % WAVE;
@@ -435,7 +536,7 @@ __global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
       }
     }
     const int64_t j0 = dt * KBN;
-    tile_scores<PREC>(xsrc, mp, norms, n, qt * KBQ, j0, include_self, smem);
+    tile_scores<PREC>(xsrc, mp, norms, scales, n, qt * KBQ, j0, include_self, smem);
     __syncthreads();
     // top-K' update: wave w owns query rows RPW*w .. RPW*w+RPW-1 of the tile.  A cheap,
     // unrolled filter marks the rows with any score below their threshold; only those
@@ -506,27 +607,40 @@ __global__ __launch_bounds__(256) void knn_rerank_kernel(
     wave_merge64(ls, lj, bs, bj);
   }
   const float s_last = rdlane(ls, kc - 1);   // every non-candidate scores >= s_last
-  // exact float32 difference-form distances of the kc candidates (lane r <- candidate r)
-  float myd = INFINITY;
-  int myj = INT_MAX;
+  // exact float32 difference-form distances of the kc candidates: every lane keeps a
+  // partial sum per candidate (lanes over columns), then one transpose-reduction leaves
+  // the total for candidate r in lane r
+  const bool valid_j = lj >= 0 && (int64_t)lj < n;
+  const int jsafe = valid_j ? lj : (int)qi;
+  float acc[KCMAX];
+#pragma unroll
+  for (int r = 0; r < KCMAX; ++r) acc[r] = 0.0f;
   const float* xq = X + qi * ldx;
-  for (int r = 0; r < kc; ++r) {
-    const int j = __builtin_amdgcn_readlane(lj, r);
-    float d = INFINITY;
-    if (j >= 0 && (int64_t)j < n) {
-      const float* xj = X + (int64_t)j * ldx;
-      float acc = 0.0f;
-      for (int64_t c = lane; c < m; c += WAVE) {
-        const float df = xq[c] - xj[c];
-        acc = fmaf(df, df, acc);
+  for (int64_t c0 = 0; c0 < m; c0 += WAVE) {
+    const int64_t c = c0 + lane;
+    const bool in = c < m;
+    const float xv = in ? xq[c] : 0.0f;
+#pragma unroll
+    for (int r = 0; r < KCMAX; ++r) {
+      if (r < kc) {
+        const int j = __builtin_amdgcn_readlane(jsafe, r);
+        const float df = xv - (in ? X[(int64_t)j * ldx + c] : 0.0f);
+        acc[r] = fmaf(df, df, acc[r]);
       }
-      d = wave_sum(acc);
-    }
-    if (lane == r) {
-      myd = d;
-      myj = (j >= 0 && (int64_t)j < n) ? j : INT_MAX;
     }
   }
+#pragma unroll
+  for (int wdt = 32; wdt >= 1; wdt >>= 1) {
+    const bool upper = (lane & wdt) != 0;
+#pragma unroll
+    for (int t = 0; t < wdt; ++t) {
+      const float send = upper ? acc[t] : acc[t + wdt];
+      const float keep = upper ? acc[t + wdt] : acc[t];
+      acc[t] = keep + __shfl_xor(send, wdt, WAVE);
+    }
+  }
+  const float myd = (lane < kc && valid_j) ? acc[0] : INFINITY;
+  const int myj = (lane < kc && valid_j) ? lj : INT_MAX;
   // order by (distance, index); the point itself (MC_INCLUDE_SELF) comes first
   float key = lane < kc ? myd : INFINITY;
   int kj = lane < kc ? myj : INT_MAX;
@@ -572,7 +686,7 @@ __global__ __launch_bounds__(256) void knn_rerank_kernel(
 // host side
 // ------------------------------------------------------------------------------------
 static int64_t knn_mp(int64_t m, int precision) {
-  const int64_t bk = precision == 0 ? GemmCfg<0>::BK : GemmCfg<1>::BK;
+  const int64_t bk = precision == 0 ? GemmCfg<0>::BK : (precision == 1 ? GemmCfg<1>::BK : GemmCfg<2>::BK);
   return ((m + bk - 1) / bk) * bk;
 }
 
@@ -608,17 +722,18 @@ KnnPlan knn_plan(int64_t n, int64_t m, int k, int kc, int precision) {
     p.smax = (int)smax;
   }
   const int64_t mp = knn_mp(m, precision);
-  const int64_t parts = 64;
+  const int64_t parts = KPARTS;
+  const size_t esz = precision == 0 ? 4 : (precision == 1 ? 2 : 1);
   size_t off = 0;
-  p.off_xc = off;     off += align256((size_t)n * mp * 4);
+  p.off_xc = off;     off += align256((size_t)n * mp * esz);     // the GEMM's input copy
   p.off_norm = off;   off += align256((size_t)n * 4);
   p.off_colsum = off; off += align256((size_t)parts * m * 8 + (size_t)m * 4);
   p.off_stats = off;  off += align256((size_t)n * 4 + 64);
   const size_t cand = (size_t)QT * p.smax * KBQ * kc * 4;
   p.off_cand_s = off; off += align256(cand);
   p.off_cand_j = off; off += align256(cand);
-  p.off_xlow = off;   off += precision == 1 ? align256((size_t)n * mp * 2) : 0;
-  p.off_scale = off;
+  p.off_xlow = off;
+  p.off_scale = off;  off += precision == 2 ? align256((size_t)n * 4) : 0;
   p.total = off;
   return p;
 }
@@ -628,17 +743,17 @@ hipError_t launch_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int k, 
                       void* ws, const KnnPlan& plan, hipStream_t stream) {
   unsigned char* base = reinterpret_cast<unsigned char*>(ws);
   const int64_t mp = knn_mp(m, precision);
-  float* xc = reinterpret_cast<float*>(base + plan.off_xc);
+  void* xc = base + plan.off_xc;
+  float* scales = precision == 2 ? reinterpret_cast<float*>(base + plan.off_scale) : nullptr;
   float* norms = reinterpret_cast<float*>(base + plan.off_norm);
   double* part = reinterpret_cast<double*>(base + plan.off_colsum);
-  float* mu = reinterpret_cast<float*>(base + plan.off_colsum + (size_t)64 * m * 8);
+  float* mu = reinterpret_cast<float*>(base + plan.off_colsum + (size_t)KPARTS * m * 8);
   float* radius = reinterpret_cast<float*>(base + plan.off_stats);
   float* stats = radius + n;
   float* cand_s = reinterpret_cast<float*>(base + plan.off_cand_s);
   int* cand_j = reinterpret_cast<int*>(base + plan.off_cand_j);
-  uint16_t* xb = reinterpret_cast<uint16_t*>(base + plan.off_xlow);
 
-  const int64_t parts = 64;
+  const int64_t parts = KPARTS;
   const int64_t rows_per = (n + parts - 1) / parts;
   const unsigned gx = (unsigned)((m + 255) / 256);
   timing_begin(0, stream);
@@ -650,7 +765,7 @@ hipError_t launch_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int k, 
   timing_end(1, stream);
   timing_begin(2, stream);
   hipLaunchKernelGGL(knn_center_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream, X, n,
-                     m, ldx, mp, mu, xc, xb, norms, radius, precision);
+                     m, ldx, mp, mu, xc, scales, norms, radius, precision);
   timing_end(2, stream);
   timing_begin(3, stream);
   hipLaunchKernelGGL(knn_stats_kernel, dim3(1), dim3(256), 0, stream, norms, radius, n, stats);
@@ -664,6 +779,8 @@ hipError_t launch_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int k, 
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_lds_bytes<0>());
     hipFuncSetAttribute(reinterpret_cast<const void*>(&knn_gemm_topk_kernel<1>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_lds_bytes<1>());
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&knn_gemm_topk_kernel<2>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_lds_bytes<2>());
     (void)hipGetLastError();
     attr_set = true;
   }
@@ -671,11 +788,15 @@ hipError_t launch_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int k, 
   timing_begin(4, stream);
   if (precision == 0) {
     hipLaunchKernelGGL(knn_gemm_topk_kernel<0>, grid, dim3(KNT), gemm_lds_bytes<0>(), stream,
-                       (const void*)xc, mp, norms, n, kc, plan.groups, plan.smax,
+                       (const void*)xc, mp, norms, scales, n, kc, plan.groups, plan.smax,
+                       include_self ? 1 : 0, cand_s, cand_j);
+  } else if (precision == 1) {
+    hipLaunchKernelGGL(knn_gemm_topk_kernel<1>, grid, dim3(KNT), gemm_lds_bytes<1>(), stream,
+                       (const void*)xc, mp, norms, scales, n, kc, plan.groups, plan.smax,
                        include_self ? 1 : 0, cand_s, cand_j);
   } else {
-    hipLaunchKernelGGL(knn_gemm_topk_kernel<1>, grid, dim3(KNT), gemm_lds_bytes<1>(), stream,
-                       (const void*)xb, mp, norms, n, kc, plan.groups, plan.smax,
+    hipLaunchKernelGGL(knn_gemm_topk_kernel<2>, grid, dim3(KNT), gemm_lds_bytes<2>(), stream,
+                       (const void*)xc, mp, norms, scales, n, kc, plan.groups, plan.smax,
                        include_self ? 1 : 0, cand_s, cand_j);
   }
   timing_end(4, stream);

@@ -56,7 +56,7 @@ const char* mc_status_string(int status) {
   switch (status) {
     case MC_OK: return "ok";
     case MC_EINVAL: return "invalid argument (null pointer, k out of [2, 32] or >= n, n or m <= 0, ldx < m, bad enum)";
-    case MC_ESHAPE: return "size beyond the int32 index range";
+    case MC_ESHAPE: return "size beyond a supported range (int32 indices; on-chip buffers of exact mode or the adjoint)";
     case MC_EPRECISION: return "precision not available for this operation";
     case MC_EWORKSPACE: return "workspace too small or not 256-byte aligned";
     case MC_ELAUNCH: return "kernel launch failed";
@@ -71,7 +71,7 @@ size_t mc_workspace_bytes(int32_t op, int64_t n, int64_t m, int32_t k, int32_t p
   if (n <= 0 || m <= 0 || k < 2 || k > MC_KMAX || (int64_t)k >= n) return 0;
   switch (op) {
     case MC_OP_KNN: {
-      if (precision != MC_FP32 && precision != MC_BF16) return 0;
+      if (precision != MC_FP32 && precision != MC_BF16 && precision != MC_FP8) return 0;
       if (rerank_factor < 1 || rerank_factor > 4) return 0;
       const int kc = k * rerank_factor;
       if (kc > 64 || (int64_t)kc >= n) return 0;
@@ -95,9 +95,7 @@ int mc_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int32_t k, int32_t
   if (st) return st;
   if (!idx_out || !ws) return MC_EINVAL;
   if (flags & ~(MC_INCLUDE_SELF | MC_STRICT)) return MC_EINVAL;
-  if (precision != MC_FP32 && precision != MC_BF16) {
-    return precision == MC_FP8 ? MC_EPRECISION : MC_EINVAL;
-  }
+  if (precision != MC_FP32 && precision != MC_BF16 && precision != MC_FP8) return MC_EINVAL;
   if (rerank_factor < 1 || rerank_factor > 4) return MC_EINVAL;
   const int kc = k * rerank_factor;
   if (kc > 64 || (int64_t)kc >= n) return MC_EINVAL;

@@ -49,8 +49,10 @@ def test_workspace_query():
     L = _lib()
     lib = L.lib()
     assert lib.mc_workspace_bytes(L.MC_OP_KNN, 20000, 784, 11, L.MC_FP32, 2) > 20000 * 784 * 4
-    assert lib.mc_workspace_bytes(L.MC_OP_KNN, 20000, 784, 11, L.MC_BF16, 2) > \
-        lib.mc_workspace_bytes(L.MC_OP_KNN, 20000, 784, 11, L.MC_FP32, 2)
+    # the GEMM input copy shrinks with the element size (float32 > bf16 > fp8)
+    w32, w16, w8 = (lib.mc_workspace_bytes(L.MC_OP_KNN, 20000, 784, 11, p, 2)
+                    for p in (L.MC_FP32, L.MC_BF16, L.MC_FP8))
+    assert w32 > w16 > w8 > 0
     assert lib.mc_workspace_bytes(L.MC_OP_KNN, 10, 4, 11, L.MC_FP32, 2) == 0     # k >= n
     assert lib.mc_workspace_bytes(L.MC_OP_KNN, 100, 4, 40, L.MC_FP32, 1) == 0    # k > 32
     assert lib.mc_workspace_bytes(L.MC_OP_KNN, 1000, 4, 20, L.MC_FP32, 4) == 0   # K' > 64
@@ -62,7 +64,7 @@ FAKE = 0x100000  # never dereferenced: validation fails before any device access
 
 @pytest.mark.parametrize("args,code", [
     (dict(X=None), 1), (dict(n=0), 1), (dict(m=0), 1), (dict(ldx=3), 1), (dict(k=1), 1),
-    (dict(k=33), 1), (dict(k=100), 1), (dict(precision=7), 1), (dict(precision=2), 3),
+    (dict(k=33), 1), (dict(k=100), 1), (dict(precision=7), 1), (dict(precision=2, rerank=1), 1),
     (dict(rerank=0), 1), (dict(rerank=5), 1), (dict(flags=8), 1), (dict(idx=None), 1),
     (dict(ws=None), 1), (dict(ws_bytes=16), 4), (dict(ws=FAKE + 8), 4),
     (dict(precision=1, rerank=1), 1), (dict(k=20, rerank=4), 1), (dict(n=2**31), 2),

@@ -84,3 +84,19 @@ def test_knn_translation_invariant_sets():
     amb = ((fa | fb).cpu().numpy() & 16) != 0
     same = np.array([set(a[i]) == set(b[i]) for i in range(1500)])
     assert np.all(same | amb)
+
+
+@pytest.mark.parametrize("name,n,m,k", [("blobs", 1500, 1024, 32), ("torus", 2100, 256, 16),
+                                        ("clusters", 1000, 784, 11)])
+def test_knn_fp8_sets(name, n, m, k):
+    """fp8 e4m3 distance GEMM with per-row scales, then the float32 re-rank of 2k candidates."""
+    import paper_2606_06329_amd as P
+    X = synth.WORKLOADS[name][0](n=n, m=m, seed=78)
+    print(f"knn fp8 {name} n={n} m={m} k={k}", flush=True)
+    idx, d2, fl = P.knn(to_dev(X), k, precision="fp8", rerank=2)
+    idx = idx.cpu().numpy()
+    fl = fl.cpu().numpy()
+    bad_big, bad_small, nbig, _ = knn_set_report(idx, X, np.arange(0, n, 3), k)
+    print(f"  mismatches: {bad_big} (gap above bound, of {nbig}), {bad_small} (below); "
+          f"uncertified {(fl & 32).astype(bool).sum()}")
+    assert bad_big == 0

@@ -148,8 +148,10 @@ int mc_curvature_fast(const float* X, int64_t n, int64_t m, int64_t ldx, const i
  * m > rank, and this ABI fixes it so results are reproducible.
  *
  * Arguments as mc_curvature_fast without `variant`; precision MC_FP32 only.
- * V_r (float64) and the centred patch are held on chip: m * (8 (k-1) + 4 k) bytes
- * must stay within about 150 KiB (e.g. m <= 1230 at k = 11), else MC_ESHAPE.
+ * V_r (float64), the gathered rows (float32) and the column means (float64) are
+ * held on chip: m * (8 (k-1) + 4 k + 8) bytes plus about 16 KiB of per-point state
+ * must stay within 150 KiB (e.g. m <= 1039 at k = 11), else MC_ESHAPE.  Centring,
+ * moments and the eigen-solve run in float64.
  */
 int mc_curvature_exact(const float* X, int64_t n, int64_t m, int64_t ldx, const int32_t* idx,
                        int32_t k, int32_t precision, uint32_t flags, float* kappa_out,
@@ -160,7 +162,9 @@ int mc_curvature_exact(const float* X, int64_t n, int64_t m, int64_t ldx, const 
  * grad_X += d(sum_i grad_kappa[i] * kappa_i)/dX with the neighbour lists held
  * fixed.  The derivative of the eigenvectors of the Gram matrix uses
  * regularised gap factors Delta/(Delta^2 + eta^2), eta = gap_eps * sigma_1;
- * gap_eps = 0 gives the exact derivative.
+ * gap_eps = 0 gives the exact derivative.  The patch moments, the eigen-solve
+ * and the adjoint algebra run in float64 (thin patches cancel strongly); only
+ * the scatter-add into grad_X is float32.
  *
  *   grad_kappa   [n] float32, device
  *   grad_X       [n x ldx] float32, device, ACCUMULATED into (atomic adds, so the

@@ -1,4 +1,4 @@
-// Adjoint of the Fast curvature (float32 path) with respect to the point coordinates,
+// Adjoint of the Fast curvature (float64 moments and adjoint algebra) with respect to the point coordinates,
 // neighbour lists held fixed: grad_X += d(sum_i gk_i kappa_i)/dX.
 //
 // The forward value is evaluated in Gram space (see curv_fast.hip):
@@ -33,17 +33,17 @@ struct BwdExtra {
   static constexpr size_t OFF_DB = OFF_UB + KK2 * 8;
   static constexpr size_t OFF_TB = OFF_DB + KK2 * 8;
   static constexpr size_t OFF_SC = OFF_TB + (size_t)KMAX * NPM * 8;   // 64 doubles of scalars
-  // floats: Theta (NPM x KMAX), Kbf, Qbf (KMAX x KMAX), rbf (KMAX)
+  // doubles for the column pass: Theta (NPM x KMAX), Kbf, Qbf (KMAX x KMAX), rbf (KMAX)
   static constexpr size_t OFF_TH = OFF_SC + 64 * 8;
-  static constexpr size_t OFF_KBF = OFF_TH + (size_t)NPM * KMAX * 4;
-  static constexpr size_t OFF_QBF = OFF_KBF + KK2 * 4;
-  static constexpr size_t OFF_RBF = OFF_QBF + KK2 * 4;
-  static constexpr size_t BYTES = OFF_RBF + (size_t)KMAX * 4 + 16;
+  static constexpr size_t OFF_KBF = OFF_TH + (size_t)NPM * KMAX * 8;
+  static constexpr size_t OFF_QBF = OFF_KBF + KK2 * 8;
+  static constexpr size_t OFF_RBF = OFF_QBF + KK2 * 8;
+  static constexpr size_t BYTES = OFF_RBF + (size_t)KMAX * 8 + 16;
 };
 
 template <int KMAX>
 struct BwdCfgSel {
-  using C = CurvCfg<KMAX, 2, 1, BwdExtra<KMAX>::BYTES>;
+  using C = CurvCfg<KMAX, 2, 1, BwdExtra<KMAX>::BYTES, 8>;   // float64 moments
 };
 
 // out[a][b] = sum_c A[a][c] B[c][b] for k x k row-major (stride KMAX) float64 matrices,
@@ -79,22 +79,22 @@ __global__ __launch_bounds__(BwdCfgSel<KMAX>::C::NT) void curv_backward_kernel(
   double* Db = reinterpret_cast<double*>(P.extra + E::OFF_DB);
   double* Tb = reinterpret_cast<double*>(P.extra + E::OFF_TB);
   double* SC = reinterpret_cast<double*>(P.extra + E::OFF_SC);
-  float* TH = reinterpret_cast<float*>(P.extra + E::OFF_TH);
-  float* Kbf = reinterpret_cast<float*>(P.extra + E::OFF_KBF);
-  float* Qbf = reinterpret_cast<float*>(P.extra + E::OFF_QBF);
-  float* rbf = reinterpret_cast<float*>(P.extra + E::OFF_RBF);
+  double* TH = reinterpret_cast<double*>(P.extra + E::OFF_TH);
+  double* Kbf = reinterpret_cast<double*>(P.extra + E::OFF_KBF);
+  double* Qbf = reinterpret_cast<double*>(P.extra + E::OFF_QBF);
+  double* rbf = reinterpret_cast<double*>(P.extra + E::OFF_RBF);
 
   const float gk = gkap[i];
   if (gk == 0.0f) return;
   double tauk, sig0;
   int pe, sweep;
-  if (patch_front<KMAX, C>(P, X, n, m, ldx, idx, k, i, tg, tauk, sig0, pe, sweep)) return;
+  if (patch_front<KMAX, C, MOM_FP64>(P, X, n, m, ldx, idx, k, i, tg, tauk, sig0, pe, sweep)) return;
   if (!(sig0 > 0.0) || tauk == 0.0 || pe == 0) return;   // degenerate: kappa = 0 locally flat
 
   const int np = k * (k + 1) / 2;
-  const float* mom = P.mom;
-  const float* Krow = mom + (k + 1) * C::NPAD;
-  const float* Qrow = mom + k * C::NPAD;
+  const double* mom = reinterpret_cast<const double*>(P.mom);
+  const double* Krow = mom + (k + 1) * C::NPAD;
+  const double* Qrow = mom + k * C::NPAD;
   const double* UT = P.UT;
   double* YB = P.YB;
   const uint16_t* PIDX = P.PIDX;
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(BwdCfgSel<KMAX>::C::NT) void curv_backward_kernel(
     gsync<C::NW>();
   }
   // r_bar_j = bb_j
-  if (tg < k) rbf[tg] = (float)(2.0 * cA * SC[16 + tg]);
+  if (tg < k) rbf[tg] = 2.0 * cA * SC[16 + tg];
 
   // ---- Ut_bar from t_range: Ut_bar[:, l] = sum_j 4 cR d_jl T_j ut_l ----------------------------
   for (int e = tg; e < k * pe; e += C::NTG) {
@@ -283,8 +283,8 @@ __global__ __launch_bounds__(BwdCfgSel<KMAX>::C::NT) void curv_backward_kernel(
   for (int e = tg; e < k * k; e += C::NTG) {
     const int a = e / k, b = e % k;
     const double kb = 0.5 * (Kb[a * KMAX + b] + Kb[b * KMAX + a]) + 0.5 * (W2[a * KMAX + b] + W2[b * KMAX + a]);
-    Kbf[a * KMAX + b] = (float)kb;
-    Qbf[a * KMAX + b] = variant == 0 ? 0.0f : (float)(cM * Rm[a * KMAX + b]);
+    Kbf[a * KMAX + b] = kb;
+    Qbf[a * KMAX + b] = variant == 0 ? 0.0 : cM * Rm[a * KMAX + b];
   }
   // ---- Theta[pair(a,b)][i] = w_ab (T_bar_i[a][b] + T_bar_a[i][b] + T_bar_b[i][a]) ----------------
   for (int e = tg; e < np * k; e += C::NTG) {
@@ -294,24 +294,25 @@ __global__ __launch_bounds__(BwdCfgSel<KMAX>::C::NT) void curv_backward_kernel(
     const int b = a + r;
     const double th = Tb[ii * E::NPM + pi] + Tb[a * E::NPM + pair_index(ii, b, k)] +
                       Tb[b * E::NPM + pair_index(ii, a, k)];
-    TH[pi * KMAX + ii] = (float)((a == b ? 1.0 : 2.0) * th);
+    TH[pi * KMAX + ii] = (a == b ? 1.0 : 2.0) * th;
   }
   gsync<C::NW>();
 
   // ---- second pass over the patch: column gradients, un-centring, scatter-add ----------------
-  const float cTf = (float)(2.0 * cT);
+  // float64 throughout: the terms cancel strongly on thin patches (small m, large k).
+  const double cT2 = 2.0 * cT;
   for (int64_t c0 = (int64_t)w * WAVE; c0 < m; c0 += (int64_t)C::NW * WAVE) {
     const int64_t c = c0 + lane;
-    float xr[KMAX];
-    load_chunk<KMAX>(xr, X, ldx, P.nb, k, m, c0, lane);
-    centre_column<KMAX>(xr, k);
-    float qc = 0.0f;
+    float xf[KMAX];
+    load_chunk<KMAX>(xf, X, ldx, P.nb, k, m, c0, lane);
+    double xr[KMAX];
+    centre_column_f64<KMAX>(xf, xr, k);              // the forward moments' centred values
+    double qc = 0.0;
 #pragma unroll
-    for (int a = 0; a < KMAX; ++a)
-      if (a < k) qc = fmaf(xr[a], xr[a], qc);
-    float g[KMAX];
+    for (int a = 0; a < KMAX; ++a) qc = fma(xr[a], xr[a], qc);
+    double g[KMAX];
 #pragma unroll
-    for (int a = 0; a < KMAX; ++a) g[a] = 0.0f;
+    for (int a = 0; a < KMAX; ++a) g[a] = 0.0;
     // sum_{a<=b} Theta[ab][i] x_a x_b
     int pi = 0;
 #pragma unroll
@@ -320,44 +321,45 @@ __global__ __launch_bounds__(BwdCfgSel<KMAX>::C::NT) void curv_backward_kernel(
 #pragma unroll
         for (int b = a; b < KMAX; ++b) {
           if (b < k) {
-            const float pab = xr[a] * xr[b];
-            const float* th = TH + pi * KMAX;
+            const double pab = xr[a] * xr[b];
+            const double* th = TH + pi * KMAX;
 #pragma unroll
-            for (int ii = 0; ii < KMAX; ++ii) g[ii] = fmaf(th[ii], pab, g[ii]);
+            for (int ii = 0; ii < KMAX; ++ii) g[ii] = fma(th[ii], pab, g[ii]);
             ++pi;
           }
         }
       }
     }
     // + 2 (K_bar x)_i + 2 q (Q_bar x)_i + 2 x_i (x^T Q_bar x) + r_bar_i + 2 cT x_i
-    float xqx = 0.0f;
-    float kx[KMAX], qx[KMAX];
+    double xqx = 0.0;
+    double qx[KMAX];
 #pragma unroll
     for (int a = 0; a < KMAX; ++a) {
-      kx[a] = 0.0f;
-      qx[a] = 0.0f;
+      double kx = 0.0, qa = 0.0;
 #pragma unroll
       for (int b = 0; b < KMAX; ++b) {
         if (a < k && b < k) {
-          kx[a] = fmaf(Kbf[a * KMAX + b], xr[b], kx[a]);
-          qx[a] = fmaf(Qbf[a * KMAX + b], xr[b], qx[a]);
+          kx = fma(Kbf[a * KMAX + b], xr[b], kx);
+          qa = fma(Qbf[a * KMAX + b], xr[b], qa);
         }
       }
-      if (a < k) xqx = fmaf(xr[a], qx[a], xqx);
+      qx[a] = qa;
+      g[a] += 2.0 * kx + rbf[a] * (a < k ? 1.0 : 0.0) + cT2 * xr[a];
+      xqx = fma(xr[a], qa, xqx);
     }
-    float mean = 0.0f;
+    double mean = 0.0;
 #pragma unroll
     for (int a = 0; a < KMAX; ++a) {
       if (a < k) {
-        g[a] += 2.0f * kx[a] + 2.0f * qc * qx[a] + 2.0f * xr[a] * xqx + rbf[a] + cTf * xr[a];
+        g[a] += 2.0 * qc * qx[a] + 2.0 * xr[a] * xqx;
         mean += g[a];
       }
     }
-    mean /= (float)k;
+    mean /= (double)k;
     if (c < m) {
 #pragma unroll
       for (int a = 0; a < KMAX; ++a)
-        if (a < k) unsafeAtomicAdd(grad + (int64_t)P.nb[a] * ldx + c, g[a] - mean);
+        if (a < k) unsafeAtomicAdd(grad + (int64_t)P.nb[a] * ldx + c, (float)(g[a] - mean));
     }
   }
 }

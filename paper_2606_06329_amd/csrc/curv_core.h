@@ -13,6 +13,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 #include "mc_device.h"
 
 namespace mc {
@@ -21,7 +23,8 @@ constexpr int FCH = 64;        // patch columns per staged chunk
 constexpr int FLDX = FCH + 1;  // LDS row stride (floats) of a staged chunk
 constexpr int JAC_MAX_SWEEPS = 40;
 
-template <int KMAX, int NW_, int PPW_, size_t EXTRA_B = 0>
+// MOMSZ: bytes per stored moment and per staged patch value (4: float32, 8: float64).
+template <int KMAX, int NW_, int PPW_, size_t EXTRA_B = 0, int MOMSZ = 4>
 struct CurvCfg {
   static constexpr int KM = KMAX;
   static constexpr int MB = (KMAX + 2 + 15) / 16;           // 16-row blocks of the LHS
@@ -37,8 +40,8 @@ struct CurvCfg {
   static constexpr int JLD = KK + 1;                        // Jacobi row stride (doubles)
   static constexpr int NPAD = NB * 16;
   // LDS layout of one point (bytes); the staged chunk and the moments share storage.
-  static constexpr size_t LHS_B = (size_t)ROWS * FLDX * 4;
-  static constexpr size_t MOM_B = (size_t)(KMAX + 2) * NPAD * 4;
+  static constexpr size_t LHS_B = (size_t)ROWS * FLDX * MOMSZ;
+  static constexpr size_t MOM_B = (size_t)(KMAX + 2) * NPAD * MOMSZ;
   static constexpr size_t U0_B = LHS_B > MOM_B ? LHS_B : MOM_B;
   static constexpr size_t OFF_JA = (U0_B + 15) & ~(size_t)15;
   static constexpr size_t OFF_JV = OFF_JA + (size_t)KK * JLD * 8;
@@ -127,6 +130,22 @@ __device__ __forceinline__ void centre_column(float (&xr)[KMAX], int k) {
     if (j < k) xr[j] -= mean;
 }
 
+// Float64 centring of one column: offsets from the first row are exact in float64, so the
+// centred values carry only the rounding of the mean.  xc[j] = X_c[j, c] (0 for j >= k).
+template <int KMAX>
+__device__ __forceinline__ void centre_column_f64(const float (&xr)[KMAX], double (&xc)[KMAX], int k) {
+  const double x0 = (double)xr[0];
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) {
+    xc[j] = j < k ? (double)xr[j] - x0 : 0.0;
+    s += xc[j];
+  }
+  const double mean = s / (double)k;
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) xc[j] = j < k ? xc[j] - mean : 0.0;
+}
+
 // Player at round-robin position `pos` in round r of the circle schedule on KK players.
 __device__ __forceinline__ int rr_player(int pos, int r, int KK) {
   if (pos == 0) return 0;
@@ -138,7 +157,7 @@ __device__ __forceinline__ int rr_player(int pos, int r, int KK) {
 // Pointers into one point's LDS region.
 struct PointLds {
   float* lhs;
-  float* mom;
+  void* mom;          // float or double moments (row-major, stride NPAD)
   double* JA;
   double* JV;
   double* UT;
@@ -158,7 +177,7 @@ template <class C>
 __device__ __forceinline__ PointLds point_lds(unsigned char* smem) {
   PointLds P;
   P.lhs = reinterpret_cast<float*>(smem);
-  P.mom = reinterpret_cast<float*>(smem);
+  P.mom = smem;
   P.JA = reinterpret_cast<double*>(smem + C::OFF_JA);
   P.JV = reinterpret_cast<double*>(smem + C::OFF_JV);
   P.UT = reinterpret_cast<double*>(smem + C::OFF_UT);
@@ -176,18 +195,29 @@ __device__ __forceinline__ PointLds point_lds(unsigned char* smem) {
   return P;
 }
 
+// Moment precision of patch_front: float32 MFMA, bf16 MFMA (float32 Gram), float64 MFMA.
+constexpr int MOM_FP32 = 0;
+constexpr int MOM_BF16 = 1;
+constexpr int MOM_FP64 = 2;
+
+template <int PREC>
+using MomT = typename std::conditional<PREC == MOM_FP64, double, float>::type;
+
 // Front half for point i: setup, moments, Jacobi, eigen order, numerical rank and Ut.
 // Returns 0 on success, or PF_NONFINITE (bad index or non-finite patch value).
 // Outputs (valid in every thread of the group): tauk = ||X_c||^2, sig0 = sigma_1,
-// pe = numerical rank, sweep = Jacobi sweeps used.
-template <int KMAX, class C, int PREC = 0>
+// pe = numerical rank, sweep = Jacobi sweeps used.  With MOM_FP64 the patch is centred,
+// staged and multiplied in float64 (centre_column_f64).
+template <int KMAX, class C, int PREC = MOM_FP32>
 __device__ uint8_t patch_front(const PointLds& P, const float* __restrict__ X, int64_t n, int64_t m,
                                int64_t ldx, const int32_t* __restrict__ idx, int k, int64_t i,
                                int tg, double& tauk, double& sig0, int& pe, int& sweep) {
+  static_assert(PREC != MOM_FP64 || sizeof(MomT<PREC>) * C::NPAD * (KMAX + 2) <= C::U0_B,
+                "float64 moments need a CurvCfg with MOMSZ = 8");
   const int w = tg / WAVE;
   const int lane = tg % WAVE;
-  float* lhs = P.lhs;
-  float* mom = P.mom;
+  MomT<PREC>* lhs = reinterpret_cast<MomT<PREC>*>(P.lhs);   // staged chunk: float64 with MOM_FP64
+  MomT<PREC>* mom = reinterpret_cast<MomT<PREC>*>(P.mom);
   double* JA = P.JA;
   double* JV = P.JV;
   int* misc = P.misc;
@@ -219,16 +249,17 @@ __device__ uint8_t patch_front(const PointLds& P, const float* __restrict__ X, i
   }
   for (int t = tg; t < k * k; t += C::NTG)
     P.PIDX[(t / k) * KMAX + t % k] = (uint16_t)pair_index(t / k, t % k, k);
-  for (int t = tg; t < (C::ROWS - (k + 2)) * FLDX; t += C::NTG) lhs[(k + 2) * FLDX + t] = 0.0f;
+  for (int t = tg; t < (C::ROWS - (k + 2)) * FLDX; t += C::NTG) lhs[(k + 2) * FLDX + t] = 0;
   gsync<C::NW>();
   if (misc[0]) return PF_NONFINITE;
 
   // ---- pass over the patch: moments on MFMA --------------------------------------
-  floatx4 acc[C::MB][C::NBW];
+  using AccT = typename std::conditional<PREC == MOM_FP64, doublex4, floatx4>::type;
+  AccT acc[C::MB][C::NBW];
 #pragma unroll
   for (int a = 0; a < C::MB; ++a)
 #pragma unroll
-    for (int b = 0; b < C::NBW; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < C::NBW; ++b) acc[a][b] = AccT{0, 0, 0, 0};
 
   int off1[C::NBW], off2[C::NBW];
 #pragma unroll
@@ -259,25 +290,56 @@ __device__ uint8_t patch_front(const PointLds& P, const float* __restrict__ X, i
 #pragma unroll
       for (int j = 0; j < KMAX; ++j)
         if (j < k) nonfinite |= !isfinite(xr[j]);
-      centre_column<KMAX>(xr, k);
-      float q = 0.0f;
+      if constexpr (PREC == MOM_FP64) {
+        double xc[KMAX];
+        centre_column_f64<KMAX>(xr, xc, k);
+        double q = 0.0;
 #pragma unroll
-      for (int j = 0; j < KMAX; ++j) {
-        if (j < k) {
-          const float xc = xr[j];
-          q = fmaf(xc, xc, q);
-          tau64 = fma((double)xc, (double)xc, tau64);
-          lhs[j * FLDX + lane] = xc;
+        for (int j = 0; j < KMAX; ++j) {
+          if (j < k) {
+            q = fma(xc[j], xc[j], q);
+            lhs[j * FLDX + lane] = xc[j];
+          }
         }
+        tau64 += q;
+        lhs[k * FLDX + lane] = q;
+      } else {
+        centre_column<KMAX>(xr, k);
+        float q = 0.0f;
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) {
+          if (j < k) {
+            const float xc = xr[j];
+            q = fmaf(xc, xc, q);
+            tau64 = fma((double)xc, (double)xc, tau64);
+            lhs[j * FLDX + lane] = xc;
+          }
+        }
+        lhs[k * FLDX + lane] = q;
       }
-      lhs[k * FLDX + lane] = q;
-      lhs[(k + 1) * FLDX + lane] = (c0 + lane < m) ? 1.0f : 0.0f;
+      lhs[(k + 1) * FLDX + lane] = (c0 + lane < m) ? 1 : 0;
     }
     gsync<C::NW>();
     if (w == 0 && c0 + FCH < m) load_chunk<KMAX>(xr, X, ldx, nb, k, m, c0 + FCH, lane);
 
     const int64_t rem = m - c0;
-    if constexpr (PREC == 0) {
+    if constexpr (PREC == MOM_FP64) {
+      const int steps = rem >= FCH ? FCH / 4 : (int)((rem + 3) / 4);
+      for (int s = 0; s < steps; ++s) {
+        const int col = 4 * s + lane / 16;
+        double av[C::MB];
+#pragma unroll
+        for (int a = 0; a < C::MB; ++a) av[a] = lhs[(16 * a + lane % 16) * FLDX + col];
+#pragma unroll
+        for (int b = 0; b < C::NBW; ++b) {
+          if (w + C::NW * b < nbr) {
+            const double bv = lhs[off1[b] + col] * lhs[off2[b] + col];
+#pragma unroll
+            for (int a = 0; a < C::MB; ++a) acc[a][b] = mfma16x16x4f64(av[a], bv, acc[a][b]);
+          }
+        }
+      }
+    } else if constexpr (PREC == MOM_FP32) {
       const int steps = rem >= FCH ? FCH / 4 : (int)((rem + 3) / 4);
       for (int s = 0; s < steps; ++s) {
         const int col = 4 * s + lane / 16;
@@ -348,12 +410,12 @@ __device__ uint8_t patch_front(const PointLds& P, const float* __restrict__ X, i
       for (int a = 0; a < C::MB; ++a)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = 16 * a + 4 * (lane / 16) + r;
-          if (row < (PREC == 0 ? k + 2 : k + 1) && col < npc) mom[row * C::NPAD + col] = acc[a][b][r];
+          const int row = 16 * a + (PREC == MOM_FP64 ? lane / 16 + 4 * r : 4 * (lane / 16) + r);
+          if (row < (PREC == MOM_BF16 ? k + 1 : k + 2) && col < npc) mom[row * C::NPAD + col] = acc[a][b][r];
         }
     }
   }
-  if constexpr (PREC != 0) {
+  if constexpr (PREC == MOM_BF16) {
     if (w == 0) {
 #pragma unroll
       for (int a = 0; a < KB; ++a)
@@ -376,7 +438,7 @@ __device__ uint8_t patch_front(const PointLds& P, const float* __restrict__ X, i
   // reads and writes the same cells and the update runs in place.
   const int KK = (k + 1) & ~1;
   const int HP = KK / 2;
-  const float* Krow = mom + (k + 1) * C::NPAD;
+  const MomT<PREC>* Krow = mom + (k + 1) * C::NPAD;
   double trace = 0.0;
   for (int e = tg; e < KK * KK; e += C::NTG) {
     const int x = e / KK, y = e % KK;
@@ -464,7 +526,8 @@ __device__ uint8_t patch_front(const PointLds& P, const float* __restrict__ X, i
   gsync<C::NW>();
   sig0 = JA[P.ord[0] * C::JLD + P.ord[0]];
   const int plim = (int)((int64_t)(k - 1) < m ? (int64_t)(k - 1) : m);
-  const double rtol = (double)(m > k ? m : k) * 0x1p-24;
+  // relative floor of the Gram eigenvalues: the rounding level of the accumulated moments
+  const double rtol = (double)(m > k ? m : k) * (PREC == MOM_FP64 ? 0x1p-44 : 0x1p-24);
   pe = 0;
   if (sig0 > 0.0) {
     while (pe < plim && JA[P.ord[pe] * C::JLD + P.ord[pe]] > rtol * sig0) ++pe;

@@ -12,8 +12,9 @@
 // alpha)/beta), held in compact WY form Q = I - Y T Y^T, so w_l = e_l - Y T y_l with y_l
 // row l of Y.  Cost O((k + p) m^2) per point instead of the eigensolver's O(m^3).
 //
-// One workgroup (4 waves) per point.  V_r (float64) and the centred patch (float32)
-// live in LDS, which bounds m * (8 p + 4 k) (checked on the host).
+// One workgroup (4 waves) per point.  V_r (float64), the gathered rows (float32) and the
+// per-column means (float64) live in LDS, which bounds m * (8 p + 4 k + 8) (checked on the
+// host).  Centred values are formed in float64 exactly as in the moment pass.
 #include "curv_core.h"
 #include "mc_internal.h"
 
@@ -23,7 +24,7 @@ constexpr size_t EXACT_LDS_MAX = 150 * 1024;   // bytes for V_r + patch + T on t
 
 template <int KMAX>
 struct ExactCfgSel {
-  using C = CurvCfg<KMAX, 4, 1, 0>;
+  using C = CurvCfg<KMAX, 4, 1, 0, 8>;   // float64 moments: an exact Gram for the basis
 };
 
 __device__ __forceinline__ double block_sum256(double v, double* red) {
@@ -48,7 +49,7 @@ __global__ __launch_bounds__(256) void curv_exact_kernel(
   const PointLds P = point_lds<C>(smem);
   double tauk, sig0;
   int pe, sweep;
-  const uint8_t bad = patch_front<KMAX, C>(P, X, n, m, ldx, idx, k, i, tg, tauk, sig0, pe, sweep);
+  const uint8_t bad = patch_front<KMAX, C, MOM_FP64>(P, X, n, m, ldx, idx, k, i, tg, tauk, sig0, pe, sweep);
   if (bad) {
     if (tg == 0) {
       kappa_out[i] = __builtin_nanf("");
@@ -69,31 +70,41 @@ __global__ __launch_bounds__(256) void curv_exact_kernel(
   }
   // exact-mode buffers after the core region
   double* Vd = reinterpret_cast<double*>(smem + C::BYTES);                 // m x pe, row-major
-  float* Xs = reinterpret_cast<float*>(smem + C::BYTES + (size_t)m * pe * 8);   // k x m
-  double* Tf = reinterpret_cast<double*>(smem + C::BYTES + (size_t)m * pe * 8 + (((size_t)k * m * 4 + 15) & ~(size_t)15));
+  float* Xs = reinterpret_cast<float*>(smem + C::BYTES + (size_t)m * pe * 8);   // k x m, raw rows
+  double* mu = reinterpret_cast<double*>(smem + C::BYTES + (size_t)m * pe * 8 +
+                                         (((size_t)k * m * 4 + 15) & ~(size_t)15));   // m column means
+  double* Tf = mu + m;
   double* tau_h = Tf + KMAX * KMAX;                                        // reflector scalars
   double* red = tau_h + KMAX;                                              // 4 doubles
   double* wv = red + 8;                                                    // KMAX doubles
 
-  // ---- centred patch into LDS (same float32 centring as the moment pass) --------------------
+  // ---- gathered rows and column means into LDS ----------------------------------------------
+  // X_c[j, c] = (Xs[j, c] - Xs[0, c]) - mu[c] in float64: the same values as the moment pass.
   for (int64_t c0 = (int64_t)(tg / WAVE) * WAVE; c0 < m; c0 += 256) {
     float xr[KMAX];
     load_chunk<KMAX>(xr, X, ldx, P.nb, k, m, c0, tg % WAVE);
-    centre_column<KMAX>(xr, k);
     const int64_t c = c0 + tg % WAVE;
     if (c < m) {
+      double s = 0.0;
 #pragma unroll
       for (int j = 0; j < KMAX; ++j)
-        if (j < k) Xs[(int64_t)j * m + c] = xr[j];
+        if (j < k) {
+          Xs[(int64_t)j * m + c] = xr[j];
+          s += (double)xr[j] - (double)xr[0];
+        }
+      mu[c] = s / (double)k;
     }
   }
   __syncthreads();
+  auto xcen = [&](int j, int64_t a) -> double {
+    return ((double)Xs[(int64_t)j * m + a] - (double)Xs[a]) - mu[a];
+  };
   // ---- V_r = X_c^T Ut (float64), and t_range = ||X_c V_r^{o2}||^2 ------------------------
   for (int64_t e = tg; e < m * pe; e += 256) {
     const int64_t a = e / pe;
     const int l = (int)(e % pe);
     double s = 0.0;
-    for (int j = 0; j < k; ++j) s = fma((double)Xs[(int64_t)j * m + a], P.UT[j * KMAX + l], s);
+    for (int j = 0; j < k; ++j) s = fma(xcen(j, a), P.UT[j * KMAX + l], s);
     Vd[a * pe + l] = s;
   }
   __syncthreads();
@@ -103,7 +114,7 @@ __global__ __launch_bounds__(256) void curv_exact_kernel(
     double s = 0.0;
     for (int64_t a = 0; a < m; ++a) {
       const double v = Vd[a * pe + l];
-      s = fma((double)Xs[(int64_t)j * m + a], v * v, s);
+      s = fma(xcen(j, a), v * v, s);
     }
     trange = fma(s, s, trange);
   }
@@ -187,9 +198,10 @@ __global__ __launch_bounds__(256) void curv_exact_kernel(
       }
       const double wa = (a == l ? 1.0 : 0.0) - yz;
       const double w2 = wa * wa;
+      const double x0 = (double)Xs[a], ma = mu[a];
 #pragma unroll
       for (int j = 0; j < KMAX; ++j)
-        if (j < k) acc[j] = fma((double)Xs[(int64_t)j * m + a], w2, acc[j]);
+        if (j < k) acc[j] = fma(((double)Xs[(int64_t)j * m + a] - x0) - ma, w2, acc[j]);
     }
 #pragma unroll
     for (int j = 0; j < KMAX; ++j)
@@ -209,7 +221,7 @@ template <int KMAX>
 static size_t exact_lds_bytes(int64_t m, int k) {
   using C = typename ExactCfgSel<KMAX>::C;
   const int p = k - 1;
-  return C::BYTES + (size_t)m * p * 8 + (((size_t)k * m * 4 + 15) & ~(size_t)15) +
+  return C::BYTES + (size_t)m * p * 8 + (((size_t)k * m * 4 + 15) & ~(size_t)15) + (size_t)m * 8 +
          (size_t)(KMAX * KMAX + KMAX + 8 + KMAX) * 8;
 }
 

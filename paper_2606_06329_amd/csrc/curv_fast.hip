@@ -32,7 +32,7 @@ template <int KMAX, class C>
 __device__ __forceinline__ void fast_terms(const PointLds& P, int k, int pe, int tg,
                                            double (&part)[5]) {
   const int np = k * (k + 1) / 2;
-  const float* mom = P.mom;
+  const float* mom = reinterpret_cast<const float*>(P.mom);
   const float* Krow = mom + (k + 1) * C::NPAD;
   const float* Qrow = mom + k * C::NPAD;
   const double* UT = P.UT;

@@ -7,6 +7,7 @@
 namespace mc {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef short shortx8 __attribute__((ext_vector_type(8)));
 typedef short shortx4 __attribute__((ext_vector_type(4)));
@@ -54,6 +55,13 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uin
 // B[l/16][l%16]; it receives D[4*(l/16)+r][l%16], r = 0..3.
 __device__ __forceinline__ floatx4 mfma16x16x4(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// D(16x16) += A(16x4) * B(4x16), fp64.  Inputs as the fp32 16x16x4 form (lane l supplies
+// A[l%16][l/16] and B[l/16][l%16]), but the result is interleaved differently: lane l
+// receives D[l/16 + 4r][l%16], r = 0..3 (checked on gfx950).
+__device__ __forceinline__ doublex4 mfma16x16x4f64(double a, double b, doublex4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
 // D(32x32) += A(32x2) * B(2x32), fp32.  Lane l supplies A[l%32][l/32] and

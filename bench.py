@@ -21,8 +21,41 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp32": 157.3, "bf16": 2500.0}   # dense MFMA TFLOP/s, MI355X
-HBM_PEAK = 8000.0                          # GB/s
+PEAK = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}   # dense MFMA TFLOP/s, MI355X
+HBM_PEAK = 8000.0                                          # GB/s
+# precision option -> (kNN GEMM precision, curvature moment precision, reported dtype)
+PRECISIONS = {"fp32": ("fp32", "fp32", "f32"), "bf16": ("bf16", "bf16", "bf16"),
+              "fp8": ("fp8", "bf16", "fp8/bf16"), "fp64": ("fp32", "fp64", "f32/f64")}
+KNN_SOURCES = ("paper_2606_06329_amd/csrc/knn.hip", "paper_2606_06329_amd/csrc/mc_device.h")
+
+
+def source_digest(paths=KNN_SOURCES):
+    """sha256 over the sources the distance-GEMM kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(workload, prec):
+    """HBM bytes per launch of knn_gemm_topk from the committed counter summary, or None when
+    there is none for this workload or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"knn_gemm_topk_{workload}_{prec}.md")
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    fields = {}
+    for line in open(path):
+        if line.startswith("- ") and ": " in line:
+            key, val = line[2:].split(": ", 1)
+            fields[key.strip().strip("`")] = val.strip().strip("`")
+    if fields.get("source_digest") != source_digest():
+        return None, "kernel changed since the counters were taken"
+    try:
+        return int(fields["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
+    except (KeyError, ValueError):
+        return None, "summary has no traffic line"
 
 
 def cpu_baseline(X, k, variant, budget_s=15.0):
@@ -54,16 +87,70 @@ def cpu_baseline(X, k, variant, budget_s=15.0):
                       f"{el:.1f} s"}, kap
 
 
+def time_path(P, _lib, torch, Xd, k, prec, mode, variant, rerank, steps, warmup):
+    """Run `steps` timed passes of the hot path (kNN + curvature) after `warmup` untimed ones.
+    Returns (ms per step, library stage timers {name: (ms, launches)}, last outputs)."""
+    kprec, cprec, _ = PRECISIONS[prec]
+    n, m = Xd.shape
+    ws = torch.empty(P.workspace_bytes(_lib.MC_OP_KNN, n, m, k, kprec, rerank),
+                     dtype=torch.uint8, device="cuda")
+
+    def step():
+        idx, _, kfl = P.knn(Xd, k, precision=kprec, rerank=rerank, ws=ws)
+        if mode == "exact":
+            kap, fl = P.curvature_exact(Xd, idx)
+        else:
+            kap, fl = P.curvature_fast(Xd, idx, variant, cprec)
+        return idx, kap, fl | kfl
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    _lib.timing_enable(True)
+    _lib.timing_read()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(steps):
+        out = step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_total = ev0.elapsed_time(ev1)
+    stages = _lib.timing_read()
+    _lib.timing_enable(False)
+    return ms_total / steps, stages, out
+
+
+def errors_vs_oracle(kap_o, idx_np, kap_np, fl_np):
+    """Per-point relative error on the oracle's sample, over points whose neighbour set equals
+    the oracle's and whose patch has full numerical rank; plus the count of differing sets."""
+    import numpy as np
+    errs, diff_sets = [], 0
+    for i, (kv, oi) in kap_o.items():
+        if set(oi.tolist()) != set(idx_np[i].tolist()):
+            diff_sets += 1
+            continue
+        if not (fl_np[i] & 4):
+            errs.append(abs(float(kap_np[i]) - kv) / kv)
+    out = {"points": len(errs), "knn_sets_differing": diff_sets}
+    if errs:
+        out.update(max_rel=float(np.max(errs)), median_rel=float(np.median(errs)))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="clusters")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--precision", default="fp32", choices=list(PRECISIONS))
     ap.add_argument("--variant", default="paper", choices=["paper", "haar"])
     ap.add_argument("--rerank", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-modes", action="store_true",
+                    help="skip the secondary measurements (other precisions, exact mode)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -82,13 +169,7 @@ def main():
     n, m = X.shape
     Xd = torch.from_numpy(X).cuda()
     prec = args.precision
-    ws = torch.empty(P.workspace_bytes(_lib.MC_OP_KNN, n, m, k, prec, args.rerank),
-                     dtype=torch.uint8, device="cuda")
-
-    def step():
-        idx, _, kfl = P.knn(Xd, k, precision=prec, rerank=args.rerank, ws=ws)
-        kap, fl = P.curvature_fast(Xd, idx, args.variant, prec)
-        return idx, kap, fl | kfl
+    kprec, cprec, dtype = PRECISIONS[prec]
 
     if args.copy_calibration:
         src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -97,33 +178,21 @@ def main():
         dst.copy_(src)                 # reads and writes exactly 256 MiB
         torch.cuda.synchronize()
         del src, dst
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    _lib.timing_enable(True)
-    _lib.timing_read()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record()
-    for _ in range(args.steps):
-        out = step()
-    ev1.record()
-    torch.cuda.synchronize()
-    ms_total = ev0.elapsed_time(ev1)
-    stages = _lib.timing_read()
-    _lib.timing_enable(False)
-    ms_step = ms_total / args.steps
-    value = n * args.steps / (ms_total / 1e3)
+
+    ms_step, stages, out = time_path(P, _lib, torch, Xd, k, prec, "fast", args.variant, args.rerank,
+                                     args.steps, args.warmup)
+    value = n / (ms_step / 1e3)
 
     gemm_ms, gemm_cnt = stages.get("knn_gemm_topk", (float("nan"), 1))
     gemm_avg = gemm_ms / gemm_cnt
     flops = 2.0 * n * n * m                      # algorithmic distance-GEMM work per launch
     achieved = flops / (gemm_avg / 1e3) / 1e12
-    roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK[prec], "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK[prec], 4), "traffic": None,
+    traffic, traffic_src = profiled_traffic(args.workload, kprec)
+    roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK[kprec], "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK[kprec], 4), "traffic": traffic,
             "kernel": "knn_gemm_topk", "kernel_ms": round(gemm_avg, 4),
-            "work": f"2*n*n*m = {flops:.4g} flop per launch"}
+            "work": f"2*n*n*m = {flops:.4g} flop per launch",
+            "traffic_source": traffic_src}
 
     idx, kap, fl = out
     kap_np = kap.cpu().numpy()
@@ -139,7 +208,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == "fp32" else "bf16",
+        "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": f"{args.workload} n={n} m={m} k={k}", "n": n, "m": m, "k": k,
                    "precision": prec, "variant": args.variant, "rerank": args.rerank,
@@ -150,17 +219,33 @@ def main():
                   "knn_uncertified": int(((fl_np & 32) != 0).sum()),
                   "knn_ambiguous": int(((fl_np & 16) != 0).sum())},
     }
+    kap_o = None
     if not args.no_cpu_baseline:
         cb, kap_o = cpu_baseline(X, k, args.variant)
         res["cpu_baseline"] = cb
-        idx_np = idx.cpu().numpy()
-        errs = []
-        for i, (kv, oi) in kap_o.items():
-            if set(oi.tolist()) == set(idx_np[i].tolist()) and not (fl_np[i] & 4):
-                errs.append(abs(kap_np[i] - kv) / kv)
-        if errs:
-            res["error_vs_oracle"] = {"points": len(errs), "max_rel": float(np.max(errs)),
-                                      "median_rel": float(np.median(errs))}
+        res["error_vs_oracle"] = errors_vs_oracle(kap_o, idx.cpu().numpy(), kap_np, fl_np)
+
+    if not args.no_modes:
+        # the same workload through the other precisions and the exact mode, timed the same way
+        modes = []
+        for mprec, mmode in (("bf16", "fast"), ("fp8", "fast"), ("fp64", "fast"), ("fp32", "exact")):
+            if (mprec, mmode) == (prec, "fast"):
+                continue
+            if mmode == "exact" and not P.exact_supported(m, k):
+                continue
+            steps = max(2, args.steps // 2)
+            mms, mst, mout = time_path(P, _lib, torch, Xd, k, mprec, mmode, args.variant, args.rerank,
+                                       steps, 1)
+            entry = {"precision": mprec, "mode": mmode, "dtype": PRECISIONS[mprec][2],
+                     "points_per_s": round(n / (mms / 1e3), 1), "ms_per_step": round(mms, 4),
+                     "stages_ms": {s: round(v[0] / v[1], 4) for s, v in mst.items()}}
+            if kap_o is not None:
+                midx, mkap, mfl = mout
+                if mmode == "fast":
+                    entry["error_vs_oracle"] = errors_vs_oracle(kap_o, midx.cpu().numpy(),
+                                                                mkap.cpu().numpy(), mfl.cpu().numpy())
+            modes.append(entry)
+        res["modes"] = modes
     print(json.dumps(res), flush=True)
 
 

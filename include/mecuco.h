@@ -53,7 +53,7 @@ extern "C" {
 /* status codes */
 #define MC_OK 0
 #define MC_EINVAL 1      /* null pointer, k < 2, k > MC_KMAX, k >= n, n or m <= 0, ldx < m, bad enum */
-#define MC_ESHAPE 2      /* size beyond the int32 index range */
+#define MC_ESHAPE 2      /* size beyond the int32 index range or an on-chip limit of the operation */
 #define MC_EPRECISION 3  /* precision not available for this operation */
 #define MC_EWORKSPACE 4  /* ws_bytes smaller than mc_workspace_bytes(...) or ws misaligned */
 #define MC_ELAUNCH 5     /* a kernel launch failed (hipGetLastError) */
@@ -64,6 +64,8 @@ extern "C" {
 #define MC_FP32 0 /* float32 inputs, float32 accumulation */
 #define MC_BF16 1 /* bfloat16 inputs, float32 accumulation */
 #define MC_FP8 2  /* OCP e4m3 inputs with per-row scales (mc_knn only), float32 accumulation */
+#define MC_FP64 3 /* float64 centring and moments (mc_curvature_fast only, k <= MC_FAST_FP64_KMAX) */
+#define MC_FAST_FP64_KMAX 28 /* the float64 moments of one point must fit in LDS */
 
 /* reading of the Fast-mode null-space term */
 #define MC_FAST_PAPER 0 /* Algorithm 1 / eqs. tnull, tA, tB as printed: t_B uses ||X_c V_r||^2, denominator D-p */
@@ -126,8 +128,11 @@ int mc_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int32_t k, int32_t
  *   idx          [n x k] int32 neighbour lists, device; entries outside [0, n)
  *                give kappa = NaN and MC_PF_NONFINITE for that point
  *   k            2 <= k <= MC_KMAX
- *   precision    MC_FP32 | MC_BF16 (patch moments on MFMA; eigen-solve and the
- *                combination are float64 in both)
+ *   precision    MC_FP32 | MC_BF16 | MC_FP64 (patch moments on MFMA; eigen-solve
+ *                and the combination are float64 in all three).  MC_FP64 centres
+ *                and accumulates in float64 (v_mfma_f64_16x16x4f64): use it for
+ *                thin or noisy patches whose Gram matrix is ill-conditioned, where
+ *                float32 moments lose digits.  k > MC_FAST_FP64_KMAX -> MC_ESHAPE
  *   variant      MC_FAST_PAPER | MC_FAST_HAAR
  *   kappa_out    [n] float32, device, written
  *   flags_out    [n] uint8 (MC_PF_* bits), or NULL
@@ -197,7 +202,10 @@ int mc_timing_enable(int on);
 int mc_timing_read(int32_t stage, double* total_ms, int64_t* launches);
 const char* mc_stage_name(int32_t stage);
 
-/* Workspace bytes needed by operation `op` (MC_OP_*) for these sizes (0 if invalid). */
+/* Workspace bytes needed by operation `op` (MC_OP_*) for these sizes; 0 if the
+ * arguments are invalid or the operation does not support them (the same cases
+ * in which the operation itself returns MC_EINVAL, MC_ESHAPE or MC_EPRECISION),
+ * so a 0 doubles as the support query. */
 size_t mc_workspace_bytes(int32_t op, int64_t n, int64_t m, int32_t k, int32_t precision,
                           int32_t rerank_factor);
 

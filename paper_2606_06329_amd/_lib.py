@@ -13,7 +13,8 @@ LIB_PATH = os.path.join(HERE, "libmecuco.so")
 
 # constants mirrored from include/mecuco.h
 MC_OK, MC_EINVAL, MC_ESHAPE, MC_EPRECISION, MC_EWORKSPACE, MC_ELAUNCH, MC_ENUMERIC, MC_EDEVICE = range(8)
-MC_FP32, MC_BF16, MC_FP8 = 0, 1, 2
+MC_FP32, MC_BF16, MC_FP8, MC_FP64 = 0, 1, 2, 3
+MC_FAST_FP64_KMAX = 28
 MC_FAST_PAPER, MC_FAST_HAAR = 0, 1
 MC_INCLUDE_SELF, MC_STRICT = 1, 2
 MC_PF_NONFINITE, MC_PF_DEGENERATE, MC_PF_RANK_DEFICIENT = 1, 2, 4

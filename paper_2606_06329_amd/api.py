@@ -13,7 +13,7 @@ import torch
 
 from . import _lib as L
 
-_PREC = {"fp32": L.MC_FP32, "bf16": L.MC_BF16, "fp8": L.MC_FP8}
+_PREC = {"fp32": L.MC_FP32, "bf16": L.MC_BF16, "fp8": L.MC_FP8, "fp64": L.MC_FP64}
 _VAR = {"paper": L.MC_FAST_PAPER, "haar": L.MC_FAST_HAAR}
 
 
@@ -79,6 +79,11 @@ def curvature_fast(X: torch.Tensor, idx: torch.Tensor, variant: str = "paper",
     return kap, fl
 
 
+def exact_supported(m: int, k: int) -> bool:
+    """Whether mc_curvature_exact accepts these sizes (its per-point state must fit on chip)."""
+    return L.lib().mc_workspace_bytes(L.MC_OP_EXACT, k + 1, m, k, L.MC_FP32, 1) > 0
+
+
 def curvature_exact(X: torch.Tensor, idx: torch.Tensor, strict: bool = False):
     """Theorem 1 with the canonical (Householder) null basis: (kappa float32 n, flags uint8 n)."""
     n, m, ldx = _cloud(X)
@@ -141,20 +146,23 @@ def curvature(X: torch.Tensor, k: int | None = None, mode: str = "auto", precisi
     """Algorithm 1 end to end: kNN graph then per-point curvature.
 
     mode "auto" selects the exact identity when D < 50 and the fast estimator otherwise.
+    precision: "fp32" | "bf16" | "fp8" (kNN GEMM in fp8, moments in bf16) | "fp64"
+    (float32 kNN, float64 moments).
     Returns (kappa, idx, flags) with flags the OR of the kNN and curvature flags.
     """
     n, m, _ = _cloud(X)
     k = default_k(n) if k is None else int(k)
     kfl = None
     if idx is None:
-        idx, _, kfl = knn(X, k, precision="fp32" if precision == "fp32" else "bf16",
-                          rerank=2 if 2 * k < n and 2 * k <= 64 else 1)
+        kprec = {"fp32": "fp32", "fp64": "fp32", "bf16": "bf16", "fp8": "fp8"}[precision]
+        idx, _, kfl = knn(X, k, precision=kprec, rerank=2 if 2 * k < n and 2 * k <= 64 else 1)
     if mode == "auto":
         mode = "exact" if m < 50 else "fast"
     if mode == "exact":
         kap, fl = curvature_exact(X, idx)
     elif mode == "fast":
-        kap, fl = curvature_fast(X, idx, variant, "bf16" if precision in ("bf16", "fp8") else "fp32")
+        cprec = {"fp32": "fp32", "fp64": "fp64", "bf16": "bf16", "fp8": "bf16"}[precision]
+        kap, fl = curvature_fast(X, idx, variant, cprec)
     else:
         raise ValueError(mode)
     if kfl is not None:

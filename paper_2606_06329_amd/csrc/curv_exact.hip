@@ -146,7 +146,9 @@ __global__ __launch_bounds__(256) void curv_exact_kernel(
     for (int c = j + 1; c < pe; ++c) {
       double d = 0.0;
       for (int64_t a = j + 1 + tg; a < m; a += 256) d = fma(Vd[a * pe + j], Vd[a * pe + c], d);
-      d = block_sum256(d, red) + Vd[(int64_t)j * pe + c];
+      // read V[j][c] before the reduction's barriers: thread 0 rewrites it right after them
+      const double vjc = Vd[(int64_t)j * pe + c];
+      d = block_sum256(d, red) + vjc;
       const double f = tauj * d;
       if (tg == 0) Vd[(int64_t)j * pe + c] -= f;
       for (int64_t a = j + 1 + tg; a < m; a += 256) Vd[a * pe + c] -= f * Vd[a * pe + j];

@@ -1,4 +1,5 @@
 // Fused Fast-mode mean curvature, one point per wave (k <= 20) or per workgroup (gfx950).
+// Moments in float32 (default), bf16 with a float32 Gram, or float64 (precision 3).
 //
 // What is computed (Fast branch of Algorithm 1, eqs. tnull/tA/tB/fast_curv):
 // for the centred k x m patch X_c of point i,
@@ -21,20 +22,26 @@
 
 namespace mc {
 
-template <int KMAX>
+template <int KMAX, int PREC>
 struct FastCfgSel {
   static constexpr int NW = KMAX <= 20 ? 1 : (KMAX <= 26 ? 2 : 4);
-  using C = CurvCfg<KMAX, NW, NW == 1 ? 4 : 1>;
+  // float64 moments double the staged chunk and the moment rows: two points per workgroup
+  static constexpr int PPW = NW == 1 ? (PREC == MOM_FP64 ? 2 : 4) : 1;
+  using C = CurvCfg<KMAX, NW, PPW, 0, PREC == MOM_FP64 ? 8 : 4>;
 };
 
+// Largest k whose float64-moment per-point state fits the 160 KiB of LDS.
+constexpr int FAST_FP64_KMAX = 28;
+
 // Gram-space terms of the Fast branch.  part[0..4] = (k-1) * (t_range, g, t_A, t_S, t_D).
-template <int KMAX, class C>
+template <int KMAX, class C, int PREC>
 __device__ __forceinline__ void fast_terms(const PointLds& P, int k, int pe, int tg,
                                            double (&part)[5]) {
   const int np = k * (k + 1) / 2;
-  const float* mom = reinterpret_cast<const float*>(P.mom);
-  const float* Krow = mom + (k + 1) * C::NPAD;
-  const float* Qrow = mom + k * C::NPAD;
+  using MT = MomT<PREC>;
+  const MT* mom = reinterpret_cast<const MT*>(P.mom);
+  const MT* Krow = mom + (k + 1) * C::NPAD;
+  const MT* Qrow = mom + k * C::NPAD;
   const double* UT = P.UT;
   double* YB = P.YB;
 #pragma unroll
@@ -53,7 +60,7 @@ __device__ __forceinline__ void fast_terms(const PointLds& P, int k, int pe, int
     part[4] = fma(UT[a * KMAX + l], qv, part[4]);
   }
   for (int j = 0; j < k; ++j) {
-    const float* Tj = mom + j * C::NPAD;
+    const MT* Tj = mom + j * C::NPAD;
     for (int e = tg; e < k * pe; e += C::NTG) {
       const int a = e / pe, l = e % pe;
       double yv = 0.0;
@@ -104,10 +111,10 @@ __device__ __forceinline__ double fast_combine(const double (&part)[5], double t
 }
 
 template <int KMAX, int PREC>
-__global__ __launch_bounds__(FastCfgSel<KMAX>::C::NT) void curv_fast_kernel(
+__global__ __launch_bounds__((FastCfgSel<KMAX, PREC>::C::NT)) void curv_fast_kernel(
     const float* __restrict__ X, int64_t n, int64_t m, int64_t ldx, const int32_t* __restrict__ idx,
     int k, int variant, float* __restrict__ kappa_out, uint8_t* __restrict__ flags_out) {
-  using C = typename FastCfgSel<KMAX>::C;
+  using C = typename FastCfgSel<KMAX, PREC>::C;
   extern __shared__ __align__(16) unsigned char smem_all[];
   const int gid = threadIdx.x / C::NTG;            // point group inside the workgroup
   const int tg = threadIdx.x % C::NTG;             // thread inside the group
@@ -126,7 +133,7 @@ __global__ __launch_bounds__(FastCfgSel<KMAX>::C::NT) void curv_fast_kernel(
     return;
   }
   double part[5];
-  fast_terms<KMAX, C>(P, k, pe, tg, part);
+  fast_terms<KMAX, C, PREC>(P, k, pe, tg, part);
 
   if (tg == 0) {
     uint8_t fl = 0;
@@ -149,10 +156,11 @@ template <int KMAX, int PREC>
 static hipError_t launch_fast_kp(const float* X, int64_t n, int64_t m, int64_t ldx,
                                  const int32_t* idx, int k, int variant, float* kappa,
                                  uint8_t* flags, hipStream_t stream) {
-  using C = typename FastCfgSel<KMAX>::C;
+  using C = typename FastCfgSel<KMAX, PREC>::C;
+  static_assert(C::PPW * C::BYTES <= 160 * 1024, "per-workgroup LDS exceeds the 160 KiB of a CU");
   static bool attr_set = false;   // LDS beyond 64 KiB needs the opt-in attribute
   if (!attr_set) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&curv_fast_kernel<KMAX, PREC>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&curv_fast_kernel<KMAX, PREC>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)(C::PPW * C::BYTES));
     (void)hipGetLastError();
     attr_set = true;
@@ -170,8 +178,13 @@ static hipError_t launch_fast_k(const float* X, int64_t n, int64_t m, int64_t ld
                                 const int32_t* idx, int k, int precision, int variant, float* kappa,
                                 uint8_t* flags, hipStream_t stream) {
   if (precision == 1)
-    return launch_fast_kp<KMAX, 1>(X, n, m, ldx, idx, k, variant, kappa, flags, stream);
-  return launch_fast_kp<KMAX, 0>(X, n, m, ldx, idx, k, variant, kappa, flags, stream);
+    return launch_fast_kp<KMAX, MOM_BF16>(X, n, m, ldx, idx, k, variant, kappa, flags, stream);
+  if (precision == 3) {
+    if constexpr (KMAX <= FAST_FP64_KMAX)
+      return launch_fast_kp<KMAX, MOM_FP64>(X, n, m, ldx, idx, k, variant, kappa, flags, stream);
+    return hipErrorInvalidValue;
+  }
+  return launch_fast_kp<KMAX, MOM_FP32>(X, n, m, ldx, idx, k, variant, kappa, flags, stream);
 }
 
 hipError_t launch_curv_fast(const float* X, int64_t n, int64_t m, int64_t ldx, const int32_t* idx,

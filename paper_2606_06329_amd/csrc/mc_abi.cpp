@@ -56,7 +56,7 @@ const char* mc_status_string(int status) {
   switch (status) {
     case MC_OK: return "ok";
     case MC_EINVAL: return "invalid argument (null pointer, k out of [2, 32] or >= n, n or m <= 0, ldx < m, bad enum)";
-    case MC_ESHAPE: return "size beyond a supported range (int32 indices; on-chip buffers of exact mode or the adjoint)";
+    case MC_ESHAPE: return "size beyond a supported range (int32 indices; on-chip buffers of exact mode, float64 Fast mode or the adjoint)";
     case MC_EPRECISION: return "precision not available for this operation";
     case MC_EWORKSPACE: return "workspace too small or not 256-byte aligned";
     case MC_ELAUNCH: return "kernel launch failed";
@@ -78,10 +78,13 @@ size_t mc_workspace_bytes(int32_t op, int64_t n, int64_t m, int32_t k, int32_t p
       return mc::knn_plan(n, m, k, kc, precision).total;
     }
     case MC_OP_FAST:
+      if (precision == MC_FP64 && k > MC_FAST_FP64_KMAX) return 0;
       return 256;  // the fused kernel keeps everything on chip
     case MC_OP_EXACT:
+      if (!mc::curv_exact_fits(m, k)) return 0;
       return mc::curv_exact_ws_bytes(n, m, k);
     case MC_OP_BACKWARD:
+      if (k > 16) return 0;
       return 256;
     default:
       return 0;
@@ -95,6 +98,7 @@ int mc_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int32_t k, int32_t
   if (st) return st;
   if (!idx_out || !ws) return MC_EINVAL;
   if (flags & ~(MC_INCLUDE_SELF | MC_STRICT)) return MC_EINVAL;
+  if (precision == MC_FP64) return MC_EPRECISION;
   if (precision != MC_FP32 && precision != MC_BF16 && precision != MC_FP8) return MC_EINVAL;
   if (rerank_factor < 1 || rerank_factor > 4) return MC_EINVAL;
   const int kc = k * rerank_factor;
@@ -121,9 +125,10 @@ int mc_curvature_fast(const float* X, int64_t n, int64_t m, int64_t ldx, const i
   if (!idx || !kappa_out) return MC_EINVAL;
   if (variant != MC_FAST_PAPER && variant != MC_FAST_HAAR) return MC_EINVAL;
   if (flags & ~MC_STRICT) return MC_EINVAL;
-  if (precision != MC_FP32 && precision != MC_BF16) {
+  if (precision != MC_FP32 && precision != MC_BF16 && precision != MC_FP64) {
     return precision == MC_FP8 ? MC_EPRECISION : MC_EINVAL;
   }
+  if (precision == MC_FP64 && k > MC_FAST_FP64_KMAX) return MC_ESHAPE;
   (void)ws;
   (void)ws_bytes;
   st = check_device();
@@ -144,7 +149,8 @@ int mc_curvature_exact(const float* X, int64_t n, int64_t m, int64_t ldx, const 
   if (!idx || !kappa_out || !ws) return MC_EINVAL;
   if (flags & ~MC_STRICT) return MC_EINVAL;
   if (precision != MC_FP32) {
-    return (precision == MC_BF16 || precision == MC_FP8) ? MC_EPRECISION : MC_EINVAL;
+    return (precision == MC_BF16 || precision == MC_FP8 || precision == MC_FP64) ? MC_EPRECISION
+                                                                                : MC_EINVAL;
   }
   if (ws_bytes < mc::curv_exact_ws_bytes(n, m, k) || misaligned(ws)) return MC_EWORKSPACE;
   if (!mc::curv_exact_fits(m, k)) return MC_ESHAPE;

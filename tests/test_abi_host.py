@@ -57,6 +57,22 @@ def test_workspace_query():
     assert lib.mc_workspace_bytes(L.MC_OP_KNN, 100, 4, 40, L.MC_FP32, 1) == 0    # k > 32
     assert lib.mc_workspace_bytes(L.MC_OP_KNN, 1000, 4, 20, L.MC_FP32, 4) == 0   # K' > 64
     assert lib.mc_workspace_bytes(7, 1000, 4, 20, L.MC_FP32, 1) == 0
+    # 0 doubles as the support query of the on-chip limits
+    assert lib.mc_workspace_bytes(L.MC_OP_EXACT, 1000, 784, 11, L.MC_FP32, 1) > 0
+    assert lib.mc_workspace_bytes(L.MC_OP_EXACT, 1000, 4096, 32, L.MC_FP32, 1) == 0
+    assert lib.mc_workspace_bytes(L.MC_OP_FAST, 1000, 64, 28, L.MC_FP64, 1) > 0
+    assert lib.mc_workspace_bytes(L.MC_OP_FAST, 1000, 64, 29, L.MC_FP64, 1) == 0
+    assert lib.mc_workspace_bytes(L.MC_OP_BACKWARD, 1000, 64, 16, L.MC_FP32, 1) > 0
+    assert lib.mc_workspace_bytes(L.MC_OP_BACKWARD, 1000, 64, 17, L.MC_FP32, 1) == 0
+    assert lib.mc_workspace_bytes(L.MC_OP_KNN, 1000, 64, 11, L.MC_FP64, 2) == 0
+
+
+def test_exact_support_boundary():
+    """The documented example: at k = 11 exact mode holds m <= 1039 on chip."""
+    L = _lib()
+    from paper_2606_06329_amd import api
+    assert api.exact_supported(1039, 11)
+    assert not api.exact_supported(1040, 11)
 
 
 FAKE = 0x100000  # never dereferenced: validation fails before any device access
@@ -68,6 +84,7 @@ FAKE = 0x100000  # never dereferenced: validation fails before any device access
     (dict(rerank=0), 1), (dict(rerank=5), 1), (dict(flags=8), 1), (dict(idx=None), 1),
     (dict(ws=None), 1), (dict(ws_bytes=16), 4), (dict(ws=FAKE + 8), 4),
     (dict(precision=1, rerank=1), 1), (dict(k=20, rerank=4), 1), (dict(n=2**31), 2),
+    (dict(precision=3), 3),
 ])
 def test_knn_rejects(args, code):
     L = _lib()
@@ -82,7 +99,7 @@ def test_knn_rejects(args, code):
 @pytest.mark.parametrize("args,code", [
     (dict(X=None), 1), (dict(idx=None), 1), (dict(kappa=None), 1), (dict(k=1), 1),
     (dict(k=100), 1), (dict(variant=2), 1), (dict(precision=2), 3), (dict(precision=9), 1),
-    (dict(flags=1), 1), (dict(ldx=2), 1),
+    (dict(flags=1), 1), (dict(ldx=2), 1), (dict(precision=3, k=29), 2), (dict(precision=3, k=32), 2),
 ])
 def test_fast_rejects(args, code):
     L = _lib()
@@ -96,7 +113,7 @@ def test_fast_rejects(args, code):
 
 @pytest.mark.parametrize("args,code", [
     (dict(X=None), 1), (dict(ws=None), 1), (dict(precision=1), 3), (dict(ws_bytes=0), 4),
-    (dict(k=2, n=2), 1),
+    (dict(k=2, n=2), 1), (dict(precision=3), 3),
 ])
 def test_exact_rejects(args, code):
     L = _lib()
@@ -110,7 +127,7 @@ def test_exact_rejects(args, code):
 
 @pytest.mark.parametrize("args,code", [
     (dict(gk=None), 1), (dict(grad=None), 1), (dict(gap=-1.0), 1), (dict(gap=float("nan")), 1),
-    (dict(variant=3), 1), (dict(k=0), 1),
+    (dict(variant=3), 1), (dict(k=0), 1), (dict(k=17), 2), (dict(k=32), 2),
 ])
 def test_backward_rejects(args, code):
     L = _lib()

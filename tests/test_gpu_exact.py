@@ -73,6 +73,9 @@ def test_exact_equals_fast_haar_when_q_is_one():
     want = np.array([oc.fast_kappa(oc.patch(X64, idx[i]), "haar") for i in range(0, 400, 7)])
     # exact path (float64 moments) against the oracle's Haar reading
     assert rel_err(ke[::7], want).max() <= TOL_FP32
+    # float64-moment Fast HAAR against the exact path, both on the GPU
+    kh64, _ = P.curvature_fast(to_dev(X), idd, "haar", "fp64")
+    assert rel_err(ke, kh64.cpu().numpy()).max() <= TOL_FP32
     # the float32-moment Fast path is looser on these thin (m = k), noisy patches: the Gram
     # matrix has condition ~1e4, so float32 moments carry ~1e-3 relative error into t_null
     assert np.median(rel_err(kh[::7], want)) <= 1e-3

@@ -1,4 +1,4 @@
-"""GPU parity of mc_curvature_fast (float32 path) against the float64 oracle.
+"""GPU parity of mc_curvature_fast (float32, float64 and bf16 moments) against the float64 oracle.
 
 Neighbour lists come from the oracle, so these tests isolate the curvature
 kernel: every point is compared element by element at sizes that span
@@ -55,6 +55,44 @@ def test_fast_fp32_parity(case, variant):
     assert np.all(np.isfinite(kap))
     assert rank_ok.mean() > 0.95
     assert err[rank_ok].max() <= TOL_FP32, (err.max(), np.argmax(err))
+
+
+@pytest.mark.parametrize("variant", ["paper", "haar"])
+def test_fast_fp64_parity(case, variant):
+    """Float64 moments: every point (including the thin, ill-conditioned ones) to 1e-6."""
+    import paper_2606_06329_amd as P
+    from paper_2606_06329_amd._lib import MecucoError
+    from tests.gpu_common import TOL_FP64
+    X, idx, k = case
+    print(f"fast fp64 parity n={X.shape[0]} m={X.shape[1]} k={k} variant={variant}", flush=True)
+    if k > 28:
+        with pytest.raises(MecucoError):
+            P.curvature_fast(to_dev(X), to_dev_idx(idx), variant, "fp64")
+        return
+    kap, fl = P.curvature_fast(to_dev(X), to_dev_idx(idx), variant, "fp64")
+    kap, fl = kap.cpu().numpy(), fl.cpu().numpy()
+    want, pe = oracle_fast(X, idx, variant)
+    rank_ok = ((fl & 4) == 0) & (pe == min(k - 1, X.shape[1]))
+    err = rel_err(kap, want)
+    print(f"  max rel err {err[rank_ok].max():.2e}", flush=True)
+    assert rank_ok.mean() > 0.95
+    assert err[rank_ok].max() <= TOL_FP64, (err.max(), np.argmax(err))
+
+
+def test_fast_fp64_thin_patches():
+    """m = k torus patches (Gram condition ~1e4): float64 moments hold 1e-6 where float32
+    moments drift to ~1e-3."""
+    import paper_2606_06329_amd as P
+    from tests.gpu_common import TOL_FP64
+    X = synth.torus(n=400, m=12, seed=3051, d=3)
+    idx, _, _, _ = ok.knn(X.astype(np.float64), 12)
+    idx = idx.astype(np.int32)
+    for variant in ("paper", "haar"):
+        kap, fl = P.curvature_fast(to_dev(X), to_dev_idx(idx), variant, "fp64")
+        want, pe = oracle_fast(X, idx, variant)
+        ok_rows = ((fl.cpu().numpy() & 4) == 0) & (pe == 11)
+        assert ok_rows.mean() > 0.95
+        assert rel_err(kap.cpu().numpy(), want)[ok_rows].max() <= TOL_FP64
 
 
 def to_dev_idx(idx):

@@ -130,87 +130,127 @@ __global__ __launch_bounds__(256) void knn_stats_kernel(const float* __restrict_
 }
 
 // ------------------------------------------------------------------------------------
-// wave-level sorted list: lane r holds the r-th smallest (score, index) of a row,
-// r = 0..63; the row's threshold is the entry of lane kc-1.
+// wave-level sorted list: lane r holds the r-th smallest key of a row, r = 0..63, and the
+// row's threshold is the entry of lane kc-1.  A key is the 64-bit integer
+// (ord(score) << 32) | index, with ord the order-preserving map of float32 onto uint32,
+// so one unsigned compare orders by (score, index) without branches.
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ float rdlane(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-__device__ __forceinline__ bool key_less(float s, int j, float s2, int j2) {
-  return s < s2 || (s == s2 && j < j2);
+__device__ __forceinline__ uint32_t rdlane_u(uint32_t v, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
 }
 
-// Insert one (s, j) that beats the threshold: lanes at or after its rank shift up by one.
-__device__ __forceinline__ void list_insert(float& ls, int& lj, float s, int j) {
-  const int lane = lane_id();
-  const int pos = __popcll(__ballot(key_less(ls, lj, s, j)));
-  const float us = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(ls), 0x138, 0xf, 0xf, false));
-  const int uj = __builtin_amdgcn_mov_dpp(lj, 0x138, 0xf, 0xf, false);   // wave_shr:1
-  if (lane > pos) {
-    ls = us;
-    lj = uj;
-  } else if (lane == pos) {
-    ls = s;
-    lj = j;
+// a < b as float32  <=>  f2ord(a) < f2ord(b) as uint32 (NaN-free inputs; +inf maps highest)
+__device__ __forceinline__ uint32_t f2ord(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ float ord2f(uint32_t o) {
+  return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
+}
+
+__device__ __forceinline__ uint64_t mkkey(uint32_t hi, uint32_t lo) {
+  return ((uint64_t)hi << 32) | (uint64_t)lo;
+}
+
+constexpr uint32_t KEY_PAD_HI = 0xFF800000u;   // ord(+inf)
+constexpr uint32_t KEY_PAD_LO = 0x7FFFFFFFu;   // INT_MAX index
+
+// Value of lane (lane ^ JJ): DPP quad permutes for 1 and 2, DPP row rotate for 8,
+// ds_swizzle (no memory access) for 4 and 16, ds_bpermute for 32.
+template <int JJ>
+__device__ __forceinline__ uint32_t xshfl(uint32_t v) {
+  if constexpr (JJ == 1) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+  } else if constexpr (JJ == 2) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  } else if constexpr (JJ == 4) {
+    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F);              // xor 4 in 32 lanes
+  } else if constexpr (JJ == 8) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);  // row_ror:8
+  } else if constexpr (JJ == 16) {
+    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);              // xor 16 in 32 lanes
+  } else {
+    static_assert(JJ == 32, "lane distance");
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((lane_id() ^ 32) << 2, (int)v);
   }
 }
 
-// Compare-exchange with the lane at distance jj; the lower lane keeps the smaller key
-// when `asc`, the larger otherwise.
-__device__ __forceinline__ void cmpx(float& s, int& j, int jj, bool asc) {
+// Insert one key that beats the threshold: lanes at or after its rank shift up by one.
+__device__ __forceinline__ void list_insert(uint32_t& hi, uint32_t& lo, uint32_t nhi, uint32_t nlo) {
   const int lane = lane_id();
-  const float so = __shfl_xor(s, jj, WAVE);
-  const int jo = __shfl_xor(j, jj, WAVE);
-  const bool lower = (lane & jj) == 0;
-  if ((lower == asc) ? key_less(so, jo, s, j) : key_less(s, j, so, jo)) {
-    s = so;
-    j = jo;
-  }
+  const int pos = __popcll(__ballot(mkkey(hi, lo) < mkkey(nhi, nlo)));
+  const uint32_t uh = (uint32_t)__builtin_amdgcn_mov_dpp((int)hi, 0x138, 0xf, 0xf, false);   // wave_shr:1
+  const uint32_t ul = (uint32_t)__builtin_amdgcn_mov_dpp((int)lo, 0x138, 0xf, 0xf, false);
+  hi = lane > pos ? uh : (lane == pos ? nhi : hi);
+  lo = lane > pos ? ul : (lane == pos ? nlo : lo);
 }
 
-// Bitonic sort of one value per lane, ascending by (score, index).
-__device__ __forceinline__ void wave_sort64(float& s, int& j) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int kk = 2; kk <= 64; kk <<= 1)
-#pragma unroll
-    for (int jj = kk >> 1; jj > 0; jj >>= 1) cmpx(s, j, jj, (lane & kk) == 0);
+// Compare-exchange with lane ^ JJ: the lower lane keeps the smaller key when `asc`, the
+// larger otherwise (keys are distinct, so one unsigned compare decides both lanes).
+template <int JJ>
+__device__ __forceinline__ void cmpx(uint32_t& hi, uint32_t& lo, bool asc) {
+  const uint32_t oh = xshfl<JJ>(hi), ol = xshfl<JJ>(lo);
+  const bool lower = (lane_id() & JJ) == 0;
+  const bool take = (mkkey(oh, ol) < mkkey(hi, lo)) != (lower != asc);
+  hi = take ? oh : hi;
+  lo = take ? ol : lo;
 }
 
-// The 64 smallest of two ascending wave lists, ascending, into (ls, lj).
-__device__ __forceinline__ void wave_merge64(float& ls, int& lj, float bs, int bj) {
+// Bitonic sort of one key per lane, ascending (ASC) or descending.
+template <bool ASC>
+__device__ __forceinline__ void wave_sort64(uint32_t& hi, uint32_t& lo) {
   const int lane = lane_id();
-  const float rs = __shfl(bs, 63 - lane, WAVE);   // reversed: [list asc | b desc] is bitonic
-  const int rj = __shfl(bj, 63 - lane, WAVE);
-  if (key_less(rs, rj, ls, lj)) {
-    ls = rs;
-    lj = rj;
-  }
-#pragma unroll
-  for (int jj = 32; jj > 0; jj >>= 1) cmpx(ls, lj, jj, true);
+#define MC_STAGE(KK, JJ) cmpx<JJ>(hi, lo, ((lane & (KK)) == 0) == ASC)
+  MC_STAGE(2, 1);
+  MC_STAGE(4, 2); MC_STAGE(4, 1);
+  MC_STAGE(8, 4); MC_STAGE(8, 2); MC_STAGE(8, 1);
+  MC_STAGE(16, 8); MC_STAGE(16, 4); MC_STAGE(16, 2); MC_STAGE(16, 1);
+  MC_STAGE(32, 16); MC_STAGE(32, 8); MC_STAGE(32, 4); MC_STAGE(32, 2); MC_STAGE(32, 1);
+  MC_STAGE(64, 32); MC_STAGE(64, 16); MC_STAGE(64, 8); MC_STAGE(64, 4); MC_STAGE(64, 2); MC_STAGE(64, 1);
+#undef MC_STAGE
 }
 
-// Filter 64 candidates (one per lane) against the row list and take in what passes.
-__device__ __forceinline__ void half_update(float& ls, int& lj, float v, int jv, int kc) {
-  float th = rdlane(ls, kc - 1);
-  uint64_t msk = __ballot(v < th);
+// The 64 smallest of an ascending list and a DESCENDING b, ascending, into (hi, lo):
+// the lane-wise minimum of the two is bitonic, and six stages sort it.
+__device__ __forceinline__ void wave_merge64(uint32_t& hi, uint32_t& lo, uint32_t bh, uint32_t bl) {
+  const bool take = mkkey(bh, bl) < mkkey(hi, lo);
+  hi = take ? bh : hi;
+  lo = take ? bl : lo;
+  cmpx<32>(hi, lo, true);
+  cmpx<16>(hi, lo, true);
+  cmpx<8>(hi, lo, true);
+  cmpx<4>(hi, lo, true);
+  cmpx<2>(hi, lo, true);
+  cmpx<1>(hi, lo, true);
+}
+
+constexpr int INSERT_MAX = 12;   // up to this many survivors go in one by one; more: sort + merge
+
+// Filter 64 candidate keys (one per lane) against the row list and take in what passes.
+__device__ __forceinline__ void half_update(uint32_t& hi, uint32_t& lo, uint32_t vh, uint32_t vl, int kc) {
+  uint32_t th = rdlane_u(hi, kc - 1);
+  uint64_t msk = __ballot(vh < th);
   if (!msk) return;
-  if (__popcll(msk) <= 6) {
+  if (__popcll(msk) <= INSERT_MAX) {
     while (msk) {
       const int src = __ffsll((unsigned long long)msk) - 1;
       msk &= msk - 1;
-      const float sv = rdlane(v, src);
-      if (sv < th) {
-        list_insert(ls, lj, sv, __builtin_amdgcn_readlane(jv, src));
-        th = rdlane(ls, kc - 1);
+      const uint32_t sh = rdlane_u(vh, src);
+      if (sh < th) {
+        list_insert(hi, lo, sh, rdlane_u(vl, src));
+        th = rdlane_u(hi, kc - 1);
       }
     }
   } else {
-    float bs = v < th ? v : INFINITY;
-    int bj = v < th ? jv : INT_MAX;
-    wave_sort64(bs, bj);
-    wave_merge64(ls, lj, bs, bj);
+    uint32_t bh = vh < th ? vh : 0xFFFFFFFFu;
+    uint32_t bl = vh < th ? vl : 0xFFFFFFFFu;
+    wave_sort64<false>(bh, bl);
+    wave_merge64(hi, lo, bh, bl);
   }
 }
 
@@ -333,14 +373,16 @@ __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64
     }
     const int col = 32 * wc + lane % 32;
     const int64_t gj = j0 + col;
-    const float nj = gj < n ? norms[gj] : 0.0f;
+    const bool colok = gj < n;
+    const int dq = (int)(j0 - q0) + col;   // column index relative to the query tile (int32)
+    const float nj = colok ? norms[gj] : 0.0f;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int row = 64 * wr + 32 * a + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
         float sc = fmaf(-2.0f, acc[a][r], nj);
-        if (gj >= n || (!include_self && gj == q0 + row)) sc = INFINITY;
+        if (!colok || (!include_self && dq == row)) sc = INFINITY;
         Ss[row * SLD + col] = sc;
       }
   } else if constexpr (PREC == 1) {
@@ -402,14 +444,16 @@ __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64
     for (int b = 0; b < 2; ++b) {
       const int col = 32 * wc + 16 * b + lane % 16;
       const int64_t gj = j0 + col;
-      const float nj = gj < n ? norms[gj] : 0.0f;
+      const bool colok = gj < n;
+      const int dq = (int)(j0 - q0) + col;
+      const float nj = colok ? norms[gj] : 0.0f;
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = 64 * wr + 16 * a + 4 * (lane / 16) + r;
           float sc = fmaf(-2.0f, acc[a][b][r], nj);
-          if (gj >= n || (!include_self && gj == q0 + row)) sc = INFINITY;
+          if (!colok || (!include_self && dq == row)) sc = INFINITY;
           Ss[row * SLD + col] = sc;
         }
     }
@@ -474,17 +518,20 @@ __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64
     for (int b = 0; b < 2; ++b) {
       const int col = 32 * wc + 16 * b + lane % 16;
       const int64_t gj = j0 + col;
-      const float nj = gj < n ? norms[gj] : 0.0f;
-      const float sj = gj < n ? scales[gj] : 0.0f;
+      const bool colok = gj < n;
+      const int dq = (int)(j0 - q0) + col;
+      const float nj = colok ? norms[gj] : 0.0f;
+      const float sj = colok ? scales[gj] : 0.0f;
+      const float* sq = scales + q0;                // row scales of the query tile
+      const int nq = (int)(n - q0 < KBQ ? n - q0 : KBQ);
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = 64 * wr + 16 * a + 4 * (lane / 16) + r;
-          const int64_t gi = q0 + row;
-          const float si = gi < n ? scales[gi] : 0.0f;
+          const float si = row < nq ? sq[row] : 0.0f;
           float sc = fmaf(-2.0f * si * sj, acc[a][b][r], nj);
-          if (gj >= n || (!include_self && gj == gi)) sc = INFINITY;
+          if (!colok || (!include_self && dq == row)) sc = INFINITY;
           Ss[row * SLD + col] = sc;
         }
     }
@@ -508,8 +555,7 @@ __global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
   const int64_t tb = (L * P) / G, te = ((L + 1) * P) / G;
   const float* Ss = reinterpret_cast<const float*>(smem);
 
-  float ls[RPW];
-  int lj[RPW];
+  uint32_t lh[RPW], ll[RPW];   // per-row sorted key lists (score order bits, index)
   int64_t cur_qt = -1;
   auto flush = [&]() {
     if (cur_qt < 0) return;
@@ -519,8 +565,8 @@ __global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
       const int64_t gi = cur_qt * KBQ + RPW * w + rr;
       if (gi < n && lane < kc) {
         const int64_t o = ((cur_qt * smax + seg) * KBQ + RPW * w + rr) * kc + lane;
-        cand_s[o] = ls[rr];
-        cand_j[o] = lj[rr];
+        cand_s[o] = ord2f(lh[rr]);
+        cand_j[o] = (int)ll[rr];
       }
     }
   };
@@ -531,8 +577,8 @@ __global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
       cur_qt = qt;
 #pragma unroll
       for (int rr = 0; rr < RPW; ++rr) {
-        ls[rr] = INFINITY;
-        lj[rr] = INT_MAX;
+        lh[rr] = KEY_PAD_HI;
+        ll[rr] = KEY_PAD_LO;
       }
     }
     const int64_t j0 = dt * KBN;
@@ -545,31 +591,28 @@ __global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
 #pragma unroll
     for (int rr = 0; rr < RPW; ++rr) {
       const int row = RPW * w + rr;
-      const float th = rdlane(ls[rr], kc - 1);
-      const bool hit = (Ss[row * SLD + lane] < th) || (Ss[row * SLD + 64 + lane] < th);
+      const uint32_t th = rdlane_u(lh[rr], kc - 1);
+      const bool hit = (f2ord(Ss[row * SLD + lane]) < th) || (f2ord(Ss[row * SLD + 64 + lane]) < th);
       need |= (__ballot(hit) != 0ull ? 1u : 0u) << rr;
     }
     while (need) {
       const int rr = __ffs(need) - 1;
       need &= need - 1;
-      float ws = ls[0];
-      int wj = lj[0];
+      uint32_t wh = lh[0], wl = ll[0];
 #pragma unroll
-      for (int r = 1; r < RPW; ++r)
-        if (rr == r) {
-          ws = ls[r];
-          wj = lj[r];
-        }
+      for (int r = 1; r < RPW; ++r) {
+        wh = rr == r ? lh[r] : wh;
+        wl = rr == r ? ll[r] : wl;
+      }
       const int row = RPW * w + rr;
 #pragma nounroll
       for (int h = 0; h < 2; ++h)
-        half_update(ws, wj, Ss[row * SLD + 64 * h + lane], (int)(j0 + 64 * h + lane), kc);
+        half_update(wh, wl, f2ord(Ss[row * SLD + 64 * h + lane]), (uint32_t)(j0 + 64 * h + lane), kc);
 #pragma unroll
-      for (int r = 0; r < RPW; ++r)
-        if (rr == r) {
-          ls[r] = ws;
-          lj[r] = wj;
-        }
+      for (int r = 0; r < RPW; ++r) {
+        lh[r] = rr == r ? wh : lh[r];
+        ll[r] = rr == r ? wl : ll[r];
+      }
     }
     __syncthreads();
   }
@@ -593,20 +636,20 @@ __global__ __launch_bounds__(256) void knn_rerank_kernel(
   const int64_t P = QT * NT;
   const int64_t qt = qi / KBQ, row = qi % KBQ;
   const int64_t nseg = range_owner(qt * NT + NT - 1, G, P) - range_owner(qt * NT, G, P) + 1;
-  // merge the segment lists (each ascending) into the 64 best
-  float ls = INFINITY;
-  int lj = INT_MAX;
+  // merge the segment lists (each ascending; read in reverse, so descending) into the 64 best
+  uint32_t lh = KEY_PAD_HI, ll = KEY_PAD_LO;
   for (int64_t sg = 0; sg < nseg; ++sg) {
     const int64_t o = ((qt * smax + sg) * KBQ + row) * kc;
-    float bs = INFINITY;
-    int bj = INT_MAX;
-    if (lane < kc) {
-      bs = cand_s[o + lane];
-      bj = cand_j[o + lane];
+    uint32_t bh = 0xFFFFFFFFu, bl = 0xFFFFFFFFu;
+    const int src = WAVE - 1 - lane;
+    if (src < kc) {
+      bh = f2ord(cand_s[o + src]);
+      bl = (uint32_t)cand_j[o + src];
     }
-    wave_merge64(ls, lj, bs, bj);
+    wave_merge64(lh, ll, bh, bl);
   }
-  const float s_last = rdlane(ls, kc - 1);   // every non-candidate scores >= s_last
+  const int lj = (int)ll;
+  const float s_last = ord2f(rdlane_u(lh, kc - 1));   // every non-candidate scores >= s_last
   // exact float32 difference-form distances of the kc candidates: every lane keeps a
   // partial sum per candidate (lanes over columns), then one transpose-reduction leaves
   // the total for candidate r in lane r
@@ -642,12 +685,13 @@ __global__ __launch_bounds__(256) void knn_rerank_kernel(
   const float myd = (lane < kc && valid_j) ? acc[0] : INFINITY;
   const int myj = (lane < kc && valid_j) ? lj : INT_MAX;
   // order by (distance, index); the point itself (MC_INCLUDE_SELF) comes first
-  float key = lane < kc ? myd : INFINITY;
-  int kj = lane < kc ? myj : INT_MAX;
-  if (include_self && kj == (int)qi) key = -1.0f;
-  wave_sort64(key, kj);
+  uint32_t sh = f2ord(lane < kc ? myd : INFINITY);
+  uint32_t sl = (uint32_t)(lane < kc ? myj : INT_MAX);
+  if (include_self && (int)sl == (int)qi) sh = f2ord(-1.0f);
+  wave_sort64<true>(sh, sl);
   // after the sort, lane r holds rank r; recover its distance
-  float dr = key;
+  const int kj = (int)sl;
+  float dr = ord2f(sh);
   if (include_self && kj == (int)qi) dr = 0.0f;
   if (lane < k) {
     idx_out[qi * k + lane] = kj;

@@ -155,7 +155,7 @@ int mc_curvature_fast(const float* X, int64_t n, int64_t m, int64_t ldx, const i
  * Arguments as mc_curvature_fast without `variant`; precision MC_FP32 only.
  * V_r (float64), the gathered rows (float32) and the column means (float64) are
  * held on chip: m * (8 (k-1) + 4 k + 8) bytes plus about 16 KiB of per-point state
- * must stay within 150 KiB (e.g. m <= 1039 at k = 11), else MC_ESHAPE.  Centring,
+ * must stay within 150 KiB (e.g. m <= 1038 at k = 11), else MC_ESHAPE.  Centring,
  * moments and the eigen-solve run in float64.
  */
 int mc_curvature_exact(const float* X, int64_t n, int64_t m, int64_t ldx, const int32_t* idx,

@@ -230,7 +230,7 @@ __global__ __launch_bounds__(BwdCfgSel<KMAX>::C::NT) void curv_backward_kernel(
 
   // ---- eigen adjoint: K_bar += U (diag(sig_bar) + F o (U^T U_bar)) U^T, F regularised ------
   // U columns in eigen order: column l of U is JV[:, ord[l]]; U_bar[:, l] = Ut_bar[:, l] sigma_l^{-1/2}
-  const int KK = (k + 1) & ~1;
+  constexpr int KK = C::KK;                         // every eigen column of the padded solve
   const double eta = (double)gap_eps * sig0;
   for (int e = tg; e < KK * pe; e += C::NTG) {
     const int x = e / pe, l = e % pe;                // M[x][l], x over all eigen columns

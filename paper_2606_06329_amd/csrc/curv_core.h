@@ -53,7 +53,8 @@ struct CurvCfg {
   static constexpr size_t N_INT = KMAX + KK + 8;                          // nb, ord, misc
   static constexpr size_t OFF_PIDX = OFF_INT + N_INT * 4;
   static constexpr size_t OFF_PJ = OFF_PIDX + (size_t)KMAX * KMAX * 2;
-  static constexpr size_t OFF_EXTRA = (OFF_PJ + 2 * NPAD + 15) & ~(size_t)15;
+  static constexpr size_t OFF_PAIR = (OFF_PJ + 2 * NPAD + 1) & ~(size_t)1;  // Jacobi pair table
+  static constexpr size_t OFF_EXTRA = (OFF_PAIR + (size_t)(KK - 1) * (KK / 2) * 2 + 15) & ~(size_t)15;
   static constexpr size_t BYTES = (OFF_EXTRA + EXTRA_B + 15) & ~(size_t)15;
 };
 
@@ -146,6 +147,14 @@ __device__ __forceinline__ void centre_column_f64(const float (&xr)[KMAX], doubl
   for (int j = 0; j < KMAX; ++j) xc[j] = j < k ? xc[j] - mean : 0.0;
 }
 
+// 1/sqrt(x) for normal x > 0: hardware estimate refined by two Newton steps (float64).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  return y;
+}
+
 // Player at round-robin position `pos` in round r of the circle schedule on KK players.
 __device__ __forceinline__ int rr_player(int pos, int r, int KK) {
   if (pos == 0) return 0;
@@ -170,6 +179,7 @@ struct PointLds {
   uint16_t* PIDX;
   unsigned char* pj1;
   unsigned char* pj2;
+  uint16_t* pairs;    // round r, slot i: p | q << 8 (p < q) of the round-robin schedule
   unsigned char* extra;
 };
 
@@ -191,6 +201,7 @@ __device__ __forceinline__ PointLds point_lds(unsigned char* smem) {
   P.PIDX = reinterpret_cast<uint16_t*>(smem + C::OFF_PIDX);
   P.pj1 = smem + C::OFF_PJ;
   P.pj2 = P.pj1 + C::NPAD;
+  P.pairs = reinterpret_cast<uint16_t*>(smem + C::OFF_PAIR);
   P.extra = smem + C::OFF_EXTRA;
   return P;
 }
@@ -433,11 +444,13 @@ __device__ uint8_t patch_front(const PointLds& P, const float* __restrict__ X, i
   if (misc[1]) return PF_NONFINITE;
 
   // ---- k x k eigen-solve: cyclic Jacobi, parallel (round-robin) order, float64 -------
-  // Each round rotates KK/2 disjoint planes.  The update works on 2 x 2 blocks of A
-  // (pair i x pair i') and on row x of V restricted to one pair, so every thread
-  // reads and writes the same cells and the update runs in place.
-  const int KK = (k + 1) & ~1;
-  const int HP = KK / 2;
+  // The matrix is padded to KK = KMAX (even) with zero rows and columns, which never
+  // rotate, so every loop bound is a compile-time constant.  Each round rotates KK/2
+  // disjoint planes; the update works on 2 x 2 blocks of A (pair i x pair i') and on row x
+  // of V restricted to one pair, so every thread reads and writes the same cells and the
+  // update runs in place.  A round whose planes are all below threshold skips its update.
+  constexpr int KK = C::KK;
+  constexpr int HP = KK / 2;
   const MomT<PREC>* Krow = mom + (k + 1) * C::NPAD;
   double trace = 0.0;
   for (int e = tg; e < KK * KK; e += C::NTG) {
@@ -445,61 +458,76 @@ __device__ uint8_t patch_front(const PointLds& P, const float* __restrict__ X, i
     JA[x * C::JLD + y] = (x < k && y < k) ? (double)Krow[P.PIDX[x * KMAX + y]] : 0.0;
     JV[x * C::JLD + y] = (x == y) ? 1.0 : 0.0;
   }
+  for (int e = tg; e < (KK - 1) * HP; e += C::NTG) {
+    const int r = e / HP, i = e % HP;
+    const int pa = rr_player(i, r, KK), pb = rr_player(KK - 1 - i, r, KK);
+    P.pairs[e] = (uint16_t)((pa < pb ? pa : pb) | ((pa < pb ? pb : pa) << 8));
+  }
   for (int x = 0; x < k; ++x) trace += (double)Krow[P.PIDX[x * KMAX + x]];
   gsync<C::NW>();
   const double floor_abs = trace * 0x1p-100;
   sweep = 0;
   for (; sweep < JAC_MAX_SWEEPS; ++sweep) {
-    if (tg == 0) misc[2] = 0;
+    int swept = 0;
     for (int r = 0; r < KK - 1; ++r) {
+      const uint16_t* pr = P.pairs + r * HP;
+      int rot = 0;
       if (tg < HP) {
-        const int pa = rr_player(tg, r, KK), pb = rr_player(KK - 1 - tg, r, KK);
-        const int p = pa < pb ? pa : pb, q = pa < pb ? pb : pa;
+        const int pq = pr[tg];
+        const int p = pq & 0xff, q = pq >> 8;
         const double app = JA[p * C::JLD + p], aqq = JA[q * C::JLD + q], apq = JA[p * C::JLD + q];
-        double c = 1.0, s = 0.0;
+        double c = 1.0, sn = 0.0;
         const double thr = fmax(0x1p-52 * sqrt(fabs(app) * fabs(aqq)), floor_abs);
         if (fabs(apq) > thr) {
-          const double theta = (aqq - app) / (2.0 * apq);
-          const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
-          c = 1.0 / sqrt(1.0 + t * t);
-          s = t * c;
-          misc[2] = 1;
+          // t = tan(phi), the smaller root of t^2 + 2 t (aqq - app)/(2 apq) - 1 = 0
+          const double d = aqq - app, e2 = 2.0 * apq;
+          const double t0 = e2 / (fabs(d) + sqrt(fma(d, d, e2 * e2)));
+          const double t = d < 0.0 ? -t0 : t0;
+          c = rsqrt_nr(fma(t, t, 1.0));
+          sn = t * c;
+          rot = 1;
         }
         P.ROT[tg] = c;
-        P.ROT[C::KK / 2 + tg] = s;
+        P.ROT[C::KK / 2 + tg] = sn;
+      }
+      rot = __any(rot);                   // the rotating lanes all sit in wave 0
+      if constexpr (C::NW > 1) {
+        if (tg == 0) misc[3 + (r & 1)] = rot;   // two slots: a skipped round has no second barrier
       }
       gsync<C::NW>();
-      // A <- J^T A J on 2 x 2 blocks; V <- V J on row pairs
-      for (int u = tg; u < HP * HP + KK * HP; u += C::NTG) {
-        if (u < HP * HP) {
-          const int bi = u / HP, bj = u % HP;
-          const int pa = rr_player(bi, r, KK), pb = rr_player(KK - 1 - bi, r, KK);
-          const int p = pa < pb ? pa : pb, q = pa < pb ? pb : pa;
-          const int qa = rr_player(bj, r, KK), qb = rr_player(KK - 1 - bj, r, KK);
-          const int p2 = qa < qb ? qa : qb, q2 = qa < qb ? qb : qa;
-          const double c = P.ROT[bi], s = P.ROT[C::KK / 2 + bi];
-          const double c2 = P.ROT[bj], s2 = P.ROT[C::KK / 2 + bj];
-          const double a00 = JA[p * C::JLD + p2], a01 = JA[p * C::JLD + q2];
-          const double a10 = JA[q * C::JLD + p2], a11 = JA[q * C::JLD + q2];
-          // columns: (p2, q2) <- (c2 a_p2 - s2 a_q2, s2 a_p2 + c2 a_q2)
-          const double m00 = c2 * a00 - s2 * a01, m01 = s2 * a00 + c2 * a01;
-          const double m10 = c2 * a10 - s2 * a11, m11 = s2 * a10 + c2 * a11;
-          // rows: (p, q) <- (c m_p - s m_q, s m_p + c m_q)
-          double n00 = c * m00 - s * m10, n01 = c * m01 - s * m11;
-          double n10 = s * m00 + c * m10, n11 = s * m01 + c * m11;
-          if (bi == bj && s != 0.0) {
-            n01 = 0.0;
-            n10 = 0.0;
-          }
-          JA[p * C::JLD + p2] = n00;
-          JA[p * C::JLD + q2] = n01;
-          JA[q * C::JLD + p2] = n10;
-          JA[q * C::JLD + q2] = n11;
-        } else {
-          const int v = u - HP * HP;
-          const int x = v / HP, bj = v % HP;
-          const int qa = rr_player(bj, r, KK), qb = rr_player(KK - 1 - bj, r, KK);
-          const int p2 = qa < qb ? qa : qb, q2 = qa < qb ? qb : qa;
+      if constexpr (C::NW > 1) rot = misc[3 + (r & 1)];
+      if (!rot) continue;                 // nothing rotates in this round
+      swept = 1;
+      // A <- J^T A J on 2 x 2 blocks
+      for (int u = tg; u < HP * HP; u += C::NTG) {
+        const int bi = u / HP, bj = u % HP;
+        const int pq1 = pr[bi], pq2 = pr[bj];
+        const int p = pq1 & 0xff, q = pq1 >> 8, p2 = pq2 & 0xff, q2 = pq2 >> 8;
+        const double c = P.ROT[bi], sn = P.ROT[C::KK / 2 + bi];
+        const double c2 = P.ROT[bj], s2 = P.ROT[C::KK / 2 + bj];
+        const double a00 = JA[p * C::JLD + p2], a01 = JA[p * C::JLD + q2];
+        const double a10 = JA[q * C::JLD + p2], a11 = JA[q * C::JLD + q2];
+        // columns: (p2, q2) <- (c2 a_p2 - s2 a_q2, s2 a_p2 + c2 a_q2)
+        const double m00 = c2 * a00 - s2 * a01, m01 = s2 * a00 + c2 * a01;
+        const double m10 = c2 * a10 - s2 * a11, m11 = s2 * a10 + c2 * a11;
+        // rows: (p, q) <- (c m_p - s m_q, s m_p + c m_q)
+        double n00 = c * m00 - sn * m10, n01 = c * m01 - sn * m11;
+        double n10 = sn * m00 + c * m10, n11 = sn * m01 + c * m11;
+        if (bi == bj && sn != 0.0) {
+          n01 = 0.0;
+          n10 = 0.0;
+        }
+        JA[p * C::JLD + p2] = n00;
+        JA[p * C::JLD + q2] = n01;
+        JA[q * C::JLD + p2] = n10;
+        JA[q * C::JLD + q2] = n11;
+      }
+      // V <- V J on the rows of the real matrix (padded rows stay unit vectors)
+      for (int u = tg; u < KK * HP; u += C::NTG) {
+        const int x = u / HP, bj = u % HP;
+        if (x < k) {
+          const int pq2 = pr[bj];
+          const int p2 = pq2 & 0xff, q2 = pq2 >> 8;
           const double c2 = P.ROT[bj], s2 = P.ROT[C::KK / 2 + bj];
           const double v0 = JV[x * C::JLD + p2], v1 = JV[x * C::JLD + q2];
           JV[x * C::JLD + p2] = c2 * v0 - s2 * v1;
@@ -508,9 +536,7 @@ __device__ uint8_t patch_front(const PointLds& P, const float* __restrict__ X, i
       }
       gsync<C::NW>();
     }
-    const int any = misc[2];
-    gsync<C::NW>();
-    if (!any) break;
+    if (!swept) break;
   }
 
   // ---- eigen order, numerical rank, Ut = U_p / sqrt(sigma) -------------------------------
@@ -532,10 +558,12 @@ __device__ uint8_t patch_front(const PointLds& P, const float* __restrict__ X, i
   if (sig0 > 0.0) {
     while (pe < plim && JA[P.ord[pe] * C::JLD + P.ord[pe]] > rtol * sig0) ++pe;
   }
-  for (int e = tg; e < k * pe; e += C::NTG) {
-    const int a = e / pe, l = e % pe;
-    const int x = P.ord[l];
-    P.UT[a * KMAX + l] = JV[a * C::JLD + x] / sqrt(JA[x * C::JLD + x]);
+  for (int e = tg; e < KMAX * KMAX; e += C::NTG) {
+    const int a = e / KMAX, l = e % KMAX;
+    if (a < k && l < pe) {
+      const int x = P.ord[l];
+      P.UT[a * KMAX + l] = JV[a * C::JLD + x] / sqrt(JA[x * C::JLD + x]);
+    }
   }
   gsync<C::NW>();
   return 0;

@@ -33,59 +33,122 @@ struct FastCfgSel {
 // Largest k whose float64-moment per-point state fits the 160 KiB of LDS.
 constexpr int FAST_FP64_KMAX = 28;
 
+// Y = M Ut for a symmetric k x k moment matrix M held as packed pairs (row `mrow` of the
+// moments), on v_mfma_f64_16x16x4f64.  The k index of step s in block bb is
+// 16 bb + 4 s + lane/16 for both operands; ub[bb][s][lb] holds Ut[16bb+4s+lane/16][16lb+lane%16]
+// (0 outside k x pe) and pix[ab][bb][s] the pair index of M[16ab+lane%16][16bb+4s+lane/16]
+// (-1 outside k x k).  Block (ab, lb) of Y comes back in the MFMA result layout: element r
+// holds Y[16ab + lane/16 + 4r][16lb + lane%16].
+template <int KB, class MT>
+__device__ __forceinline__ void gram_times_ut(const MT* __restrict__ mrow, const int (&pix)[KB][KB][4],
+                                              const double (&ub)[KB][4][KB], doublex4 (&y)[KB][KB]) {
+#pragma unroll
+  for (int ab = 0; ab < KB; ++ab)
+#pragma unroll
+    for (int lb = 0; lb < KB; ++lb) y[ab][lb] = doublex4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ab = 0; ab < KB; ++ab)
+#pragma unroll
+    for (int bb = 0; bb < KB; ++bb)
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int pi = pix[ab][bb][st];
+        const double mv = pi >= 0 ? (double)mrow[pi] : 0.0;
+#pragma unroll
+        for (int lb = 0; lb < KB; ++lb) y[ab][lb] = mfma16x16x4f64(mv, ub[bb][st][lb], y[ab][lb]);
+      }
+}
+
 // Gram-space terms of the Fast branch.  part[0..4] = (k-1) * (t_range, g, t_A, t_S, t_D).
+// Per neighbour j, G_j = Ut^T (T_j Ut) is two chained f64 MFMA products: the result layout
+// of T_j Ut is exactly the B-operand layout of the second product, so G_j never leaves
+// registers.  The waves of a point take the j in turn; the diagonals of the G_j go to LDS
+// (over the Jacobi matrix, no longer needed) for the traces in b_j = r_j - tr G_j.
 template <int KMAX, class C, int PREC>
 __device__ __forceinline__ void fast_terms(const PointLds& P, int k, int pe, int tg,
                                            double (&part)[5]) {
+  constexpr int KB = (KMAX + 15) / 16;
   const int np = k * (k + 1) / 2;
+  const int w = tg / WAVE, lane = tg % WAVE;
   using MT = MomT<PREC>;
   const MT* mom = reinterpret_cast<const MT*>(P.mom);
-  const MT* Krow = mom + (k + 1) * C::NPAD;
-  const MT* Qrow = mom + k * C::NPAD;
   const double* UT = P.UT;
-  double* YB = P.YB;
+  double* Dg = P.JA;                   // Dg[j * JLD + l] = G_j[l][l]
+  int pix[KB][KB][4];
+  double ub[KB][4][KB];
+#pragma unroll
+  for (int ab = 0; ab < KB; ++ab)
+#pragma unroll
+    for (int bb = 0; bb < KB; ++bb)
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int a = 16 * ab + lane % 16, b = 16 * bb + 4 * st + lane / 16;
+        pix[ab][bb][st] = (a < k && b < k) ? (int)P.PIDX[a * KMAX + b] : -1;
+      }
+#pragma unroll
+  for (int bb = 0; bb < KB; ++bb)
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+      for (int lb = 0; lb < KB; ++lb) {
+        const int b = 16 * bb + 4 * st + lane / 16, l = 16 * lb + lane % 16;
+        ub[bb][st][lb] = (b < k && l < pe) ? UT[b * KMAX + l] : 0.0;
+      }
 #pragma unroll
   for (int t = 0; t < 5; ++t) part[t] = 0.0;
-  // t_S = sum_l ||K ut_l||^2 ; t_D = sum_l ut_l^T Q ut_l
-  for (int e = tg; e < k * pe; e += C::NTG) {
-    const int a = e / pe, l = e % pe;
-    double kv = 0.0, qv = 0.0;
-    for (int b = 0; b < k; ++b) {
-      const int pb = P.PIDX[a * KMAX + b];
-      const double u = UT[b * KMAX + l];
-      kv = fma((double)Krow[pb], u, kv);
-      qv = fma((double)Qrow[pb], u, qv);
-    }
-    part[3] = fma(kv, kv, part[3]);
-    part[4] = fma(UT[a * KMAX + l], qv, part[4]);
+  doublex4 y[KB][KB];
+  // t_S = sum_l ||K ut_l||^2 (wave 0);  t_D = sum_l ut_l^T Q ut_l (wave 1 % NW)
+  if (w == 0) {
+    gram_times_ut<KB>(mom + (k + 1) * C::NPAD, pix, ub, y);
+#pragma unroll
+    for (int ab = 0; ab < KB; ++ab)
+#pragma unroll
+      for (int lb = 0; lb < KB; ++lb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) part[3] = fma(y[ab][lb][r], y[ab][lb][r], part[3]);
   }
-  for (int j = 0; j < k; ++j) {
-    const MT* Tj = mom + j * C::NPAD;
-    for (int e = tg; e < k * pe; e += C::NTG) {
-      const int a = e / pe, l = e % pe;
-      double yv = 0.0;
-      for (int b = 0; b < k; ++b) yv = fma((double)Tj[P.PIDX[a * KMAX + b]], UT[b * KMAX + l], yv);
-      YB[a * KMAX + l] = yv;
-    }
-    gsync<C::NW>();
-    double trg = 0.0;
-    for (int e = tg; e < pe * pe; e += C::NTG) {
-      const int l1 = e / pe, l2 = e % pe;
-      double gv = 0.0;
-      for (int a = 0; a < k; ++a) gv = fma(UT[a * KMAX + l1], YB[a * KMAX + l2], gv);
-      part[1] = fma(gv, gv, part[1]);
-      if (l1 == l2) {
-        part[0] = fma(gv, gv, part[0]);
-        trg += gv;
+  if (w == 1 % C::NW) {
+    gram_times_ut<KB>(mom + k * C::NPAD, pix, ub, y);
+#pragma unroll
+    for (int ab = 0; ab < KB; ++ab)
+#pragma unroll
+      for (int lb = 0; lb < KB; ++lb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = 16 * ab + lane / 16 + 4 * r, l = 16 * lb + lane % 16;
+          const double u = (a < k && l < pe) ? UT[a * KMAX + l] : 0.0;
+          part[4] = fma(u, y[ab][lb][r], part[4]);
+        }
+  }
+  for (int j = w; j < k; j += C::NW) {
+    gram_times_ut<KB>(mom + j * C::NPAD, pix, ub, y);
+    // G_j = Ut^T Y: A operand Ut^T[16 l1b + lane%16][16 ab + 4 s + lane/16] = ub[ab][s][l1b]
+#pragma unroll
+    for (int l1b = 0; l1b < KB; ++l1b)
+#pragma unroll
+      for (int l2b = 0; l2b < KB; ++l2b) {
+        doublex4 g = doublex4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ab = 0; ab < KB; ++ab)
+#pragma unroll
+          for (int st = 0; st < 4; ++st) g = mfma16x16x4f64(ub[ab][st][l1b], y[ab][l2b][st], g);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          part[1] = fma(g[r], g[r], part[1]);
+          const int l1 = 16 * l1b + lane / 16 + 4 * r, l2 = 16 * l2b + lane % 16;
+          if (l1 == l2) {
+            part[0] = fma(g[r], g[r], part[0]);
+            if (l1 < pe) Dg[j * C::JLD + l1] = g[r];
+          }
+        }
       }
-    }
-    double tv[1] = {trg};
-    group_sum<C::NW, 1>(tv, P.RED, tg);
-    if (tg == 0) {
-      const double bj = (double)mom[j * C::NPAD + np] - tv[0];   // (X_c d_P)_j
-      part[2] = fma(bj, bj, part[2]);
-    }
-    gsync<C::NW>();
+  }
+  gsync<C::NW>();
+  for (int j = tg; j < k; j += C::NTG) {
+    double tr = 0.0;
+    for (int l = 0; l < pe; ++l) tr += Dg[j * C::JLD + l];
+    const double bj = (double)mom[j * C::NPAD + np] - tr;   // (X_c d_P)_j
+    part[2] = fma(bj, bj, part[2]);
   }
   group_sum<C::NW, 5>(part, P.RED, tg);
 }

@@ -68,11 +68,11 @@ def test_workspace_query():
 
 
 def test_exact_support_boundary():
-    """The documented example: at k = 11 exact mode holds m <= 1039 on chip."""
+    """The documented example: at k = 11 exact mode holds m <= 1038 on chip."""
     L = _lib()
     from paper_2606_06329_amd import api
-    assert api.exact_supported(1039, 11)
-    assert not api.exact_supported(1040, 11)
+    assert api.exact_supported(1038, 11)
+    assert not api.exact_supported(1039, 11)
 
 
 FAKE = 0x100000  # never dereferenced: validation fails before any device access

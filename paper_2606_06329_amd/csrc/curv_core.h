@@ -20,7 +20,8 @@
 namespace mc {
 
 constexpr int FCH = 64;        // patch columns per staged chunk
-constexpr int FLDX = FCH + 1;  // LDS row stride (floats) of a staged chunk
+constexpr int FLDX = FCH + 4;  // LDS row stride of a staged chunk: 16-byte rows for vector reads,
+                               // rows 4 banks apart so 8 lanes of a 128-bit read never collide
 constexpr int JAC_MAX_SWEEPS = 40;
 
 // MOMSZ: bytes per stored moment and per staged patch value (4: float32, 8: float64).
@@ -351,18 +352,25 @@ __device__ uint8_t patch_front(const PointLds& P, const float* __restrict__ X, i
         }
       }
     } else if constexpr (PREC == MOM_FP32) {
-      const int steps = rem >= FCH ? FCH / 4 : (int)((rem + 3) / 4);
-      for (int s = 0; s < steps; ++s) {
-        const int col = 4 * s + lane / 16;
-        float av[C::MB];
+      // 16-column groups; lane l supplies column 4 (l / 16) + s of the group at step s, so
+      // each operand row is one 128-bit read per group (A and B use the same column order)
+      const int ngrp = rem >= FCH ? FCH / 16 : (int)((rem + 15) / 16);
+      for (int g = 0; g < ngrp; ++g) {
+        const int col = 16 * g + 4 * (lane / 16);
+        floatx4 av[C::MB];
 #pragma unroll
-        for (int a = 0; a < C::MB; ++a) av[a] = lhs[(16 * a + lane % 16) * FLDX + col];
+        for (int a = 0; a < C::MB; ++a)
+          av[a] = *reinterpret_cast<const floatx4*>(lhs + (16 * a + lane % 16) * FLDX + col);
 #pragma unroll
         for (int b = 0; b < C::NBW; ++b) {
           if (w + C::NW * b < nbr) {
-            const float bv = lhs[off1[b] + col] * lhs[off2[b] + col];
+            const floatx4 x1 = *reinterpret_cast<const floatx4*>(lhs + off1[b] + col);
+            const floatx4 x2 = *reinterpret_cast<const floatx4*>(lhs + off2[b] + col);
+            const floatx4 bv = x1 * x2;
 #pragma unroll
-            for (int a = 0; a < C::MB; ++a) acc[a][b] = mfma16x16x4(av[a], bv, acc[a][b]);
+            for (int st = 0; st < 4; ++st)
+#pragma unroll
+              for (int a = 0; a < C::MB; ++a) acc[a][b] = mfma16x16x4(av[a][st], bv[st], acc[a][b]);
           }
         }
       }

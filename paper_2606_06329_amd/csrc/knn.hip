@@ -269,27 +269,72 @@ template <int PREC>
 struct GemmCfg;
 template <>
 struct GemmCfg<0> {
+  static constexpr int ESZ = 4;                 // bytes per element
   static constexpr int BK = 16;                 // columns per stage
   static constexpr int ALD = BK + 4;            // staging row stride (elements)
-  static constexpr size_t STAGE_B = (size_t)2 * (KBQ + KBN) * ALD * 4;
 };
 template <>
 struct GemmCfg<1> {
+  static constexpr int ESZ = 2;
   static constexpr int BK = 64;
   static constexpr int ALD = BK + 8;
-  static constexpr size_t STAGE_B = (size_t)2 * (KBQ + KBN) * ALD * 2;
 };
 template <>
 struct GemmCfg<2> {
+  static constexpr int ESZ = 1;
   static constexpr int BK = 128;                // fp8 bytes per row per stage
   static constexpr int ALD = BK + 16;
-  static constexpr size_t STAGE_B = (size_t)2 * (KBQ + KBN) * ALD;
 };
+
+// One stage of the staged operands: 256 rows (queries, then database points) of BK
+// elements, moved as 16-byte chunks, NPRE per thread.
+template <int PREC>
+struct Stage {
+  using G = GemmCfg<PREC>;
+  static constexpr int CPR = G::BK * G::ESZ / 16;                  // chunks per row
+  static constexpr int NPRE = (KBQ + KBN) * CPR / KNT;
+  static constexpr size_t BUF_B = (size_t)(KBQ + KBN) * G::ALD * G::ESZ;
+  static constexpr size_t STAGE_B = 2 * BUF_B;                     // double buffered
+};
+
+// Global -> registers: stage `ch` of query tile q0 and database tile j0 (rows past n are 0).
+template <int PREC>
+__device__ __forceinline__ void stage_load(uint4 (&pre)[Stage<PREC>::NPRE], const void* __restrict__ xsrc,
+                                           int64_t mp, int64_t n, int64_t q0, int64_t j0, int ch) {
+  using S = Stage<PREC>;
+  using G = GemmCfg<PREC>;
+  const unsigned char* xs = reinterpret_cast<const unsigned char*>(xsrc);
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < S::NPRE; ++u) {
+    const int f = tid + u * KNT;
+    const int row = f / S::CPR, c = f % S::CPR;
+    const int64_t g = row < KBQ ? q0 + row : j0 + (row - KBQ);
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (g < n)
+      v = *reinterpret_cast<const uint4*>(xs + (g * mp + (int64_t)ch * G::BK) * G::ESZ + 16 * c);
+    pre[u] = v;
+  }
+}
+
+// Registers -> LDS staging buffer `buf`.
+template <int PREC>
+__device__ __forceinline__ void stage_store(const uint4 (&pre)[Stage<PREC>::NPRE], unsigned char* smem, int buf) {
+  using S = Stage<PREC>;
+  using G = GemmCfg<PREC>;
+  unsigned char* base = smem + (size_t)buf * S::BUF_B;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < S::NPRE; ++u) {
+    const int f = tid + u * KNT;
+    *reinterpret_cast<uint4*>(base + (f / S::CPR) * (G::ALD * G::ESZ) + 16 * (f % S::CPR)) = pre[u];
+  }
+}
 
 template <int PREC>
 constexpr size_t gemm_lds_bytes() {
-  return GemmCfg<PREC>::STAGE_B > (size_t)KBQ * SLD * 4 ? GemmCfg<PREC>::STAGE_B
-                                                         : (size_t)KBQ * SLD * 4;
+  return Stage<PREC>::STAGE_B > (size_t)KBQ * SLD * 4 ? Stage<PREC>::STAGE_B
+                                                       : (size_t)KBQ * SLD * 4;
 }
 
 // Workgroup holding tile pair t under the range schedule (floor((t+1)G - 1)/P).
@@ -298,12 +343,14 @@ __host__ __device__ __forceinline__ int64_t range_owner(int64_t t, int64_t G, in
 }
 
 // Scores s[i][j] = ||y_j||^2 - 2 x_i . y_j of one 128 x 128 tile into Ss (LDS).
-// 8 waves as 2 (query rows) x 4 (db columns); wave tile 64 x 32.
+// 8 waves as 2 (query rows) x 4 (db columns); wave tile 64 x 32.  On entry `pre` holds
+// stage 0 of this tile (the caller loads it early, behind the previous tile's top-K').
 template <int PREC>
 __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64_t mp,
                                             const float* __restrict__ norms,
                                             const float* __restrict__ scales, int64_t n, int64_t q0,
-                                            int64_t j0, int include_self, unsigned char* smem) {
+                                            int64_t j0, int include_self, unsigned char* smem,
+                                            uint4 (&pre)[Stage<PREC>::NPRE]) {
   using G = GemmCfg<PREC>;
   const int tid = threadIdx.x;
   const int w = tid / WAVE, lane = tid % WAVE;
@@ -311,40 +358,16 @@ __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64
   float* Ss = reinterpret_cast<float*>(smem);
   const int nch = (int)(mp / G::BK);
   if constexpr (PREC == 0) {
-    const float* xs = reinterpret_cast<const float*>(xsrc);
     float* As = reinterpret_cast<float*>(smem);
     floatx16 acc[2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][r] = 0.0f;
-    // staging: 128 query rows + 128 db rows, 16 floats each = 1024 float4; 2 per thread
-    float4 pre[2];
-    auto gload = [&](int ch) {
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int f = tid + u * KNT;
-        const int row = f / 4;           // 0..255: queries then db rows
-        const int c4 = f % 4;
-        const int64_t g = row < KBQ ? q0 + row : j0 + (row - KBQ);
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (g < n) v = *reinterpret_cast<const float4*>(xs + g * mp + (int64_t)ch * G::BK + 4 * c4);
-        pre[u] = v;
-      }
-    };
-    auto sstore = [&](int buf) {
-      float* base = As + (size_t)buf * (KBQ + KBN) * G::ALD;
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int f = tid + u * KNT;
-        *reinterpret_cast<float4*>(base + (f / 4) * G::ALD + 4 * (f % 4)) = pre[u];
-      }
-    };
-    gload(0);
-    sstore(0);
+    stage_store<PREC>(pre, smem, 0);
     __syncthreads();
     for (int ch = 0; ch < nch; ++ch) {
-      if (ch + 1 < nch) gload(ch + 1);
+      if (ch + 1 < nch) stage_load<PREC>(pre, xsrc, mp, n, q0, j0, ch + 1);
       const float* base = As + (size_t)(ch & 1) * (KBQ + KBN) * G::ALD;
       const int h = lane / 32;
       float av[2][8], bv[8];
@@ -368,7 +391,7 @@ __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64
       for (int st = 0; st < 8; ++st)
 #pragma unroll
         for (int a = 0; a < 2; ++a) acc[a] = mfma32x32x2(av[a][st], bv[st], acc[a]);
-      if (ch + 1 < nch) sstore((ch + 1) & 1);
+      if (ch + 1 < nch) stage_store<PREC>(pre, smem, (ch + 1) & 1);
       __syncthreads();
     }
     const int col = 32 * wc + lane % 32;
@@ -386,40 +409,16 @@ __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64
         Ss[row * SLD + col] = sc;
       }
   } else if constexpr (PREC == 1) {
-    const uint16_t* xs = reinterpret_cast<const uint16_t*>(xsrc);
     uint16_t* As = reinterpret_cast<uint16_t*>(smem);
     floatx4 acc[4][2];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
-    // staging: 256 rows x 64 bf16 = 2048 chunks of 16 B; 4 per thread
-    uint4 pre[4];
-    auto gload = [&](int ch) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int f = tid + u * KNT;
-        const int row = f / 8;
-        const int c8 = f % 8;
-        const int64_t g = row < KBQ ? q0 + row : j0 + (row - KBQ);
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (g < n) v = *reinterpret_cast<const uint4*>(xs + g * mp + (int64_t)ch * G::BK + 8 * c8);
-        pre[u] = v;
-      }
-    };
-    auto sstore = [&](int buf) {
-      uint16_t* base = As + (size_t)buf * (KBQ + KBN) * G::ALD;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int f = tid + u * KNT;
-        *reinterpret_cast<uint4*>(base + (f / 8) * G::ALD + 8 * (f % 8)) = pre[u];
-      }
-    };
-    gload(0);
-    sstore(0);
+    stage_store<PREC>(pre, smem, 0);
     __syncthreads();
     for (int ch = 0; ch < nch; ++ch) {
-      if (ch + 1 < nch) gload(ch + 1);
+      if (ch + 1 < nch) stage_load<PREC>(pre, xsrc, mp, n, q0, j0, ch + 1);
       const uint16_t* base = As + (size_t)(ch & 1) * (KBQ + KBN) * G::ALD;
 #pragma unroll
       for (int kk = 0; kk < 2; ++kk) {           // two 32-wide k steps per stage
@@ -437,7 +436,7 @@ __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64
 #pragma unroll
           for (int b = 0; b < 2; ++b) acc[a][b] = mfma16x16x32bf16(av[a], bv[b], acc[a][b]);
       }
-      if (ch + 1 < nch) sstore((ch + 1) & 1);
+      if (ch + 1 < nch) stage_store<PREC>(pre, smem, (ch + 1) & 1);
       __syncthreads();
     }
 #pragma unroll
@@ -459,40 +458,16 @@ __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64
     }
   } else {
     // fp8 e4m3 (OCP) with per-row scales: x ~ s_i * x8_i, dot = s_i s_j (x8_i . x8_j)
-    const uint8_t* xs = reinterpret_cast<const uint8_t*>(xsrc);
     uint8_t* As = reinterpret_cast<uint8_t*>(smem);
     floatx4 acc[4][2];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
-    // staging: 256 rows x 128 bytes = 2048 chunks of 16 B; 4 per thread
-    uint4 pre[4];
-    auto gload = [&](int ch) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int f = tid + u * KNT;
-        const int row = f / 8;
-        const int c16 = f % 8;
-        const int64_t g = row < KBQ ? q0 + row : j0 + (row - KBQ);
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (g < n) v = *reinterpret_cast<const uint4*>(xs + g * mp + (int64_t)ch * G::BK + 16 * c16);
-        pre[u] = v;
-      }
-    };
-    auto sstore = [&](int buf) {
-      uint8_t* base = As + (size_t)buf * (KBQ + KBN) * G::ALD;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int f = tid + u * KNT;
-        *reinterpret_cast<uint4*>(base + (f / 8) * G::ALD + 16 * (f % 8)) = pre[u];
-      }
-    };
-    gload(0);
-    sstore(0);
+    stage_store<PREC>(pre, smem, 0);
     __syncthreads();
     for (int ch = 0; ch < nch; ++ch) {
-      if (ch + 1 < nch) gload(ch + 1);
+      if (ch + 1 < nch) stage_load<PREC>(pre, xsrc, mp, n, q0, j0, ch + 1);
       const uint8_t* base = As + (size_t)(ch & 1) * (KBQ + KBN) * G::ALD;
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {           // four 32-wide k steps per stage
@@ -511,7 +486,7 @@ __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64
           for (int b = 0; b < 2; ++b)
             acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av[a], bv[b], acc[a][b], 0, 0, 0);
       }
-      if (ch + 1 < nch) sstore((ch + 1) & 1);
+      if (ch + 1 < nch) stage_store<PREC>(pre, smem, (ch + 1) & 1);
       __syncthreads();
     }
 #pragma unroll
@@ -570,6 +545,8 @@ __global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
       }
     }
   };
+  uint4 pre[Stage<PREC>::NPRE];
+  if (tb < te) stage_load<PREC>(pre, xsrc, mp, n, (tb / NT) * KBQ, (tb % NT) * KBN, 0);
   for (int64_t t = tb; t < te; ++t) {
     const int64_t qt = t / NT, dt = t % NT;
     if (qt != cur_qt) {
@@ -582,8 +559,10 @@ __global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
       }
     }
     const int64_t j0 = dt * KBN;
-    tile_scores<PREC>(xsrc, mp, norms, scales, n, qt * KBQ, j0, include_self, smem);
+    tile_scores<PREC>(xsrc, mp, norms, scales, n, qt * KBQ, j0, include_self, smem, pre);
     __syncthreads();
+    // stage 0 of the next tile is fetched now and lands behind the top-K' work below
+    if (t + 1 < te) stage_load<PREC>(pre, xsrc, mp, n, ((t + 1) / NT) * KBQ, ((t + 1) % NT) * KBN, 0);
     // top-K' update: wave w owns query rows RPW*w .. RPW*w+RPW-1 of the tile.  A cheap,
     // unrolled filter marks the rows with any score below their threshold; only those
     // rows are then swapped into working registers and updated (one copy of the code).

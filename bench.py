@@ -92,6 +92,8 @@ def time_path(P, _lib, torch, Xd, k, prec, mode, variant, rerank, steps, warmup)
     Returns (ms per step, library stage timers {name: (ms, launches)}, last outputs)."""
     kprec, cprec, _ = PRECISIONS[prec]
     n, m = Xd.shape
+    if rerank is None:
+        rerank = P.default_rerank(k, n, kprec)
     ws = torch.empty(P.workspace_bytes(_lib.MC_OP_KNN, n, m, k, kprec, rerank),
                      dtype=torch.uint8, device="cuda")
 
@@ -119,7 +121,7 @@ def time_path(P, _lib, torch, Xd, k, prec, mode, variant, rerank, steps, warmup)
     ms_total = ev0.elapsed_time(ev1)
     stages = _lib.timing_read()
     _lib.timing_enable(False)
-    return ms_total / steps, stages, out
+    return ms_total / steps, stages, out, rerank
 
 
 def errors_vs_oracle(kap_o, idx_np, kap_np, fl_np):
@@ -139,6 +141,75 @@ def errors_vs_oracle(kap_o, idx_np, kap_np, fl_np):
     return out
 
 
+def oracle_sample(X, k, rows, variant):
+    """Oracle neighbour lists and Fast kappa of the sampled rows (float64 from the float32 input)."""
+    import numpy as np
+
+    from oracle import curvature as oc
+    from oracle import knn as ok
+
+    X64 = X.astype(np.float64)
+    idx, _, _, _ = ok.knn_rows(X64, rows, k)
+    kap = {int(i): (oc.fast_kappa(oc.patch(X64, idx[r]), variant), idx[r]) for r, i in enumerate(rows)}
+    return kap
+
+
+def suite(args):
+    """Secondary configurations, one JSON line each: the other workloads at their own sizes and
+    precision paths, errors against the oracle on a sampled set of points."""
+    import numpy as np
+    import torch
+
+    import paper_2606_06329_amd as P
+    from paper_2606_06329_amd import _lib, synth
+
+    plan = [("sphere", ("fp32",), True), ("torus", ("fp32", "bf16"), False),
+            ("swissroll", ("fp32",), False), ("blobs", ("fp32", "fp8"), False)]
+    for name, precs, with_exact in plan:
+        X, k = synth.make(name)
+        n, m = X.shape
+        Xd = torch.from_numpy(X).cuda()
+        rows = np.random.default_rng(11).choice(n, min(n, 120 if m < 1000 else 40), replace=False)
+        t0 = time.perf_counter()
+        kap_o = oracle_sample(X, k, rows, args.variant)
+        t_or = (time.perf_counter() - t0) / len(rows)
+        for prec in precs:
+            steps = 2 if n * n * m > 1e12 else 5
+            ms, st, out, rr = time_path(P, _lib, torch, Xd, k, prec, "fast", args.variant, None, steps, 1)
+            idx, kap, fl = out
+            line = {"suite": name, "n": n, "m": m, "k": k, "precision": prec, "mode": "fast",
+                    "dtype": PRECISIONS[prec][2], "rerank": rr, "points_per_s": round(n / (ms / 1e3), 1),
+                    "ms_per_step": round(ms, 4),
+                    "stages_ms": {a: round(v[0] / v[1], 4) for a, v in st.items()},
+                    "error_vs_oracle": errors_vs_oracle(kap_o, idx.cpu().numpy(), kap.cpu().numpy(),
+                                                        fl.cpu().numpy()),
+                    "oracle_s_per_point_1core": round(t_or, 4)}
+            if name == "swissroll":
+                # forward + adjoint of sum_i w_i kappa_i, neighbour lists fixed
+                w = torch.from_numpy(synth.loss_weights(n)).cuda()
+                g = torch.zeros_like(Xd)
+                for _ in range(2):
+                    P.curvature_backward(Xd, idx, w, args.variant, 0.0, g)
+                torch.cuda.synchronize()
+                _lib.timing_enable(True)
+                _lib.timing_read()
+                for _ in range(steps):
+                    P.curvature_backward(Xd, idx, w, args.variant, 0.0, g)
+                torch.cuda.synchronize()
+                bt = _lib.timing_read()
+                _lib.timing_enable(False)
+                b_ms, b_cnt = bt.get("curv_backward", (float("nan"), 1))
+                line["backward_ms"] = round(b_ms / b_cnt, 4)
+            print(json.dumps(line), flush=True)
+        if with_exact:
+            ms, st, out, rr = time_path(P, _lib, torch, Xd, k, "fp32", "exact", args.variant, None, 5, 1)
+            print(json.dumps({"suite": name, "n": n, "m": m, "k": k, "precision": "fp32", "mode": "exact",
+                              "points_per_s": round(n / (ms / 1e3), 1), "ms_per_step": round(ms, 4),
+                              "stages_ms": {a: round(v[0] / v[1], 4) for a, v in st.items()}}), flush=True)
+        del Xd
+        torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,10 +218,13 @@ def main():
     ap.add_argument("--workload", default="clusters")
     ap.add_argument("--precision", default="fp32", choices=list(PRECISIONS))
     ap.add_argument("--variant", default="paper", choices=["paper", "haar"])
-    ap.add_argument("--rerank", type=int, default=2)
+    ap.add_argument("--rerank", type=int, default=None,
+                    help="candidates per neighbour for the float32 re-rank (default: per precision)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the secondary measurements (other precisions, exact mode)")
+    ap.add_argument("--suite", action="store_true",
+                    help="instead of the headline line, one line per secondary configuration")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -158,6 +232,10 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               f"(multi-GPU sharding is design-only)", file=sys.stderr)
         sys.exit(2)
+
+    if args.suite:
+        suite(args)
+        return
 
     import numpy as np
     import torch
@@ -179,8 +257,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    ms_step, stages, out = time_path(P, _lib, torch, Xd, k, prec, "fast", args.variant, args.rerank,
-                                     args.steps, args.warmup)
+    ms_step, stages, out, rerank = time_path(P, _lib, torch, Xd, k, prec, "fast", args.variant,
+                                             args.rerank, args.steps, args.warmup)
     value = n / (ms_step / 1e3)
 
     gemm_ms, gemm_cnt = stages.get("knn_gemm_topk", (float("nan"), 1))
@@ -211,7 +289,7 @@ def main():
         "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": f"{args.workload} n={n} m={m} k={k}", "n": n, "m": m, "k": k,
-                   "precision": prec, "variant": args.variant, "rerank": args.rerank,
+                   "precision": prec, "variant": args.variant, "rerank": rerank,
                    "mode": "fast"},
         "roofline": roof,
         "stages_ms": {s: round(v[0] / v[1], 4) for s, v in stages.items()},
@@ -234,9 +312,9 @@ def main():
             if mmode == "exact" and not P.exact_supported(m, k):
                 continue
             steps = max(2, args.steps // 2)
-            mms, mst, mout = time_path(P, _lib, torch, Xd, k, mprec, mmode, args.variant, args.rerank,
-                                       steps, 1)
-            entry = {"precision": mprec, "mode": mmode, "dtype": PRECISIONS[mprec][2],
+            mms, mst, mout, mrr = time_path(P, _lib, torch, Xd, k, mprec, mmode, args.variant,
+                                            args.rerank, steps, 1)
+            entry = {"precision": mprec, "mode": mmode, "dtype": PRECISIONS[mprec][2], "rerank": mrr,
                      "points_per_s": round(n / (mms / 1e3), 1), "ms_per_step": round(mms, 4),
                      "stages_ms": {s: round(v[0] / v[1], 4) for s, v in mst.items()}}
             if kap_o is not None:

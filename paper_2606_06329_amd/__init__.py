@@ -6,4 +6,5 @@ Importing the package does not load the library; the first call does, and
 fails loudly if it has not been built.
 """
 from .api import (MeanCurvature, curvature, curvature_backward, curvature_exact,  # noqa: F401
-                  curvature_fast, default_k, exact_supported, knn, workspace_bytes)
+                  curvature_fast, default_k, default_rerank, exact_supported, knn,
+                  workspace_bytes)

@@ -46,10 +46,25 @@ def workspace_bytes(op: int, n: int, m: int, k: int, precision: str = "fp32", re
     return int(L.lib().mc_workspace_bytes(op, n, m, k, _PREC[precision], rerank))
 
 
-def knn(X: torch.Tensor, k: int, precision: str = "fp32", rerank: int = 2,
+def default_rerank(k: int, n: int, precision: str = "fp32") -> int:
+    """Candidates per neighbour for the float32 re-rank: 2 on the float32 and bf16 GEMMs; fp8
+    keeps as many as the 64-entry lists allow (up to 4), since e4m3 scores order close
+    neighbours coarsely."""
+    r = 2 if precision in ("fp32", "bf16") else max(2, min(4, 64 // max(k, 1)))
+    while r > 1 and r * k >= n:
+        r -= 1
+    return r
+
+
+def knn(X: torch.Tensor, k: int, precision: str = "fp32", rerank: int | None = None,
         include_self: bool = False, strict: bool = False, ws: torch.Tensor | None = None):
-    """k nearest neighbours of every row of X (Step 1): (idx int32 n x k, d2 float32 n x k, flags uint8 n)."""
+    """k nearest neighbours of every row of X (Step 1): (idx int32 n x k, d2 float32 n x k, flags uint8 n).
+
+    rerank: candidates per neighbour kept from the GEMM for the float32 re-rank (None: default_rerank).
+    """
     n, m, ldx = _cloud(X)
+    if rerank is None:
+        rerank = default_rerank(k, n, precision)
     idx = torch.empty((n, k), dtype=torch.int32, device=X.device)
     d2 = torch.empty((n, k), dtype=torch.float32, device=X.device)
     fl = torch.empty((n,), dtype=torch.uint8, device=X.device)
@@ -155,7 +170,7 @@ def curvature(X: torch.Tensor, k: int | None = None, mode: str = "auto", precisi
     kfl = None
     if idx is None:
         kprec = {"fp32": "fp32", "fp64": "fp32", "bf16": "bf16", "fp8": "fp8"}[precision]
-        idx, _, kfl = knn(X, k, precision=kprec, rerank=2 if 2 * k < n and 2 * k <= 64 else 1)
+        idx, _, kfl = knn(X, k, precision=kprec)
     if mode == "auto":
         mode = "exact" if m < 50 else "fast"
     if mode == "exact":

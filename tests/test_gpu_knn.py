@@ -100,3 +100,21 @@ def test_knn_fp8_sets(name, n, m, k):
     print(f"  mismatches: {bad_big} (gap above bound, of {nbig}), {bad_small} (below); "
           f"uncertified {(fl & 32).astype(bool).sum()}")
     assert bad_big == 0
+
+
+@pytest.mark.parametrize("name,precision", [("clusters", "bf16"), ("blobs", "fp8")])
+def test_knn_low_precision_full_size(name, precision):
+    """Each low-precision GEMM at the full size of the workload it is meant for (bf16: the
+    20000 x 784 clusters; fp8 with per-row scales: the 50000 x 4096 blobs, k = 32, 64
+    candidates): sets exact on sampled rows wherever the k-th / (k+1)-th gap exceeds the
+    float32 bound."""
+    import paper_2606_06329_amd as P
+    X, k = synth.make(name)
+    n = X.shape[0]
+    print(f"knn {precision} {name} full size, rerank {P.default_rerank(k, n, precision)}", flush=True)
+    idx, _, fl = P.knn(to_dev(X), k, precision=precision)
+    idx = idx.cpu().numpy()
+    rows = np.random.default_rng(5).choice(n, 100 if X.shape[1] < 1000 else 30, replace=False)
+    bad_big, bad_small, nbig, _ = knn_set_report(idx, X, rows, k)
+    print(f"  mismatches: {bad_big} (gap above bound, of {nbig}), {bad_small} (below)", flush=True)
+    assert bad_big == 0

@@ -254,6 +254,52 @@ __device__ __forceinline__ void half_update(uint32_t& hi, uint32_t& lo, uint32_t
   }
 }
 
+// Take in the survivors of a row's 128 candidates (two 64-lane halves).  Few survivors go
+// in one by one; up to 64 are packed into one vector (forward permute), sorted and merged
+// once; more than 64 (early tiles) fall back to one sort + merge per half.
+__device__ __forceinline__ void row_update(uint32_t& hi, uint32_t& lo, uint32_t vh0, uint32_t vl0,
+                                           uint32_t vh1, uint32_t vl1, int kc) {
+  uint32_t th = rdlane_u(hi, kc - 1);
+  const uint64_t m0 = __ballot(vh0 < th), m1 = __ballot(vh1 < th);
+  const int c0 = __popcll(m0), c = c0 + __popcll(m1);
+  if (c == 0) return;
+  if (c <= INSERT_MAX) {
+#pragma nounroll
+    for (int h = 0; h < 2; ++h) {
+      uint64_t msk = h == 0 ? m0 : m1;
+      const uint32_t vh = h == 0 ? vh0 : vh1, vl = h == 0 ? vl0 : vl1;
+      while (msk) {
+        const int src = __ffsll((unsigned long long)msk) - 1;
+        msk &= msk - 1;
+        const uint32_t sh = rdlane_u(vh, src);
+        if (sh < th) {
+          list_insert(hi, lo, sh, rdlane_u(vl, src));
+          th = rdlane_u(hi, kc - 1);
+        }
+      }
+    }
+  } else if (c <= WAVE) {
+    const int lane = lane_id();
+    const uint64_t below = (1ull << lane) - 1ull;
+    const bool s0 = (m0 >> lane) & 1ull, s1 = (m1 >> lane) & 1ull;
+    // survivor ranks: half 0 fills lanes [0, c0), half 1 fills [c0, c); others go to a lane
+    // whose received value is ignored
+    const int d0 = s0 ? __popcll(m0 & below) : WAVE - 1;
+    const int d1 = s1 ? c0 + __popcll(m1 & below) : (c0 > 0 ? 0 : WAVE - 1);
+    const uint32_t p0h = (uint32_t)__builtin_amdgcn_ds_permute(d0 << 2, (int)vh0);
+    const uint32_t p0l = (uint32_t)__builtin_amdgcn_ds_permute(d0 << 2, (int)vl0);
+    const uint32_t p1h = (uint32_t)__builtin_amdgcn_ds_permute(d1 << 2, (int)vh1);
+    const uint32_t p1l = (uint32_t)__builtin_amdgcn_ds_permute(d1 << 2, (int)vl1);
+    uint32_t bh = lane < c0 ? p0h : (lane < c ? p1h : 0xFFFFFFFFu);
+    uint32_t bl = lane < c0 ? p0l : (lane < c ? p1l : 0xFFFFFFFFu);
+    wave_sort64<false>(bh, bl);
+    wave_merge64(hi, lo, bh, bl);
+  } else {
+    half_update(hi, lo, vh0, vl0, kc);
+    half_update(hi, lo, vh1, vl1, kc);
+  }
+}
+
 // ------------------------------------------------------------------------------------
 // GEMM + top-K'.  PREC 0: fp32 MFMA 32x32x2, BK = 16; PREC 1: bf16 MFMA 16x16x32, BK = 64.
 //
@@ -584,9 +630,8 @@ __global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
         wl = rr == r ? ll[r] : wl;
       }
       const int row = RPW * w + rr;
-#pragma nounroll
-      for (int h = 0; h < 2; ++h)
-        half_update(wh, wl, f2ord(Ss[row * SLD + 64 * h + lane]), (uint32_t)(j0 + 64 * h + lane), kc);
+      row_update(wh, wl, f2ord(Ss[row * SLD + lane]), (uint32_t)(j0 + lane),
+                 f2ord(Ss[row * SLD + 64 + lane]), (uint32_t)(j0 + 64 + lane), kc);
 #pragma unroll
       for (int r = 0; r < RPW; ++r) {
         lh[r] = rr == r ? wh : lh[r];

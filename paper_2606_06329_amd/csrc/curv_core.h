@@ -207,6 +207,134 @@ __device__ __forceinline__ PointLds point_lds(unsigned char* smem) {
   return P;
 }
 
+// k x k eigen-solve: cyclic Jacobi in parallel (round-robin) order, float64.  On entry
+// JA holds K (k x k, zero-padded to KK) and JV the identity.  The matrix is padded to
+// KK = KMAX (even) with zero rows and columns, which never rotate, so every loop bound is
+// a compile-time constant.  Each round rotates KK/2 disjoint planes; the update works on
+// 2 x 2 blocks of A (pair i x pair i') and on row x of V restricted to one pair, so every
+// thread reads and writes the same cells and the update runs in place.  A round whose
+// planes are all below threshold skips its update.  On return: eigen order in P.ord,
+// sig0 = sigma_1, pe = numerical rank (eigenvalues above max(k, m) * unit * sigma_1 among
+// the first min(k-1, m)), sweep = sweeps used, and P.UT = U_p diag(sigma_p^(-1/2)).
+template <int KMAX, class C>
+__device__ void jacobi_eigen(const PointLds& P, int k, int64_t m, int tg, double unit, double& sig0,
+                             int& pe, int& sweep) {
+  double* JA = P.JA;
+  double* JV = P.JV;
+  int* misc = P.misc;
+  constexpr int KK = C::KK;
+  constexpr int HP = KK / 2;
+  double trace = 0.0;
+  for (int e = tg; e < (KK - 1) * HP; e += C::NTG) {
+    const int r = e / HP, i = e % HP;
+    const int pa = rr_player(i, r, KK), pb = rr_player(KK - 1 - i, r, KK);
+    P.pairs[e] = (uint16_t)((pa < pb ? pa : pb) | ((pa < pb ? pb : pa) << 8));
+  }
+  gsync<C::NW>();
+  for (int x = 0; x < k; ++x) trace += JA[x * C::JLD + x];
+  const double floor_abs = trace * 0x1p-100;
+  sweep = 0;
+  for (; sweep < JAC_MAX_SWEEPS; ++sweep) {
+    int swept = 0;
+    for (int r = 0; r < KK - 1; ++r) {
+      const uint16_t* pr = P.pairs + r * HP;
+      int rot = 0;
+      if (tg < HP) {
+        const int pq = pr[tg];
+        const int p = pq & 0xff, q = pq >> 8;
+        const double app = JA[p * C::JLD + p], aqq = JA[q * C::JLD + q], apq = JA[p * C::JLD + q];
+        double c = 1.0, sn = 0.0;
+        const double thr = fmax(0x1p-52 * sqrt(fabs(app) * fabs(aqq)), floor_abs);
+        if (fabs(apq) > thr) {
+          // t = tan(phi), the smaller root of t^2 + 2 t (aqq - app)/(2 apq) - 1 = 0
+          const double d = aqq - app, e2 = 2.0 * apq;
+          const double t0 = e2 / (fabs(d) + sqrt(fma(d, d, e2 * e2)));
+          const double t = d < 0.0 ? -t0 : t0;
+          c = rsqrt_nr(fma(t, t, 1.0));
+          sn = t * c;
+          rot = 1;
+        }
+        P.ROT[tg] = c;
+        P.ROT[C::KK / 2 + tg] = sn;
+      }
+      rot = __any(rot);                   // the rotating lanes all sit in wave 0
+      if constexpr (C::NW > 1) {
+        if (tg == 0) misc[3 + (r & 1)] = rot;   // two slots: a skipped round has no second barrier
+      }
+      gsync<C::NW>();
+      if constexpr (C::NW > 1) rot = misc[3 + (r & 1)];
+      if (!rot) continue;                 // nothing rotates in this round
+      swept = 1;
+      // A <- J^T A J on 2 x 2 blocks
+      for (int u = tg; u < HP * HP; u += C::NTG) {
+        const int bi = u / HP, bj = u % HP;
+        const int pq1 = pr[bi], pq2 = pr[bj];
+        const int p = pq1 & 0xff, q = pq1 >> 8, p2 = pq2 & 0xff, q2 = pq2 >> 8;
+        const double c = P.ROT[bi], sn = P.ROT[C::KK / 2 + bi];
+        const double c2 = P.ROT[bj], s2 = P.ROT[C::KK / 2 + bj];
+        const double a00 = JA[p * C::JLD + p2], a01 = JA[p * C::JLD + q2];
+        const double a10 = JA[q * C::JLD + p2], a11 = JA[q * C::JLD + q2];
+        // columns: (p2, q2) <- (c2 a_p2 - s2 a_q2, s2 a_p2 + c2 a_q2)
+        const double m00 = c2 * a00 - s2 * a01, m01 = s2 * a00 + c2 * a01;
+        const double m10 = c2 * a10 - s2 * a11, m11 = s2 * a10 + c2 * a11;
+        // rows: (p, q) <- (c m_p - s m_q, s m_p + c m_q)
+        double n00 = c * m00 - sn * m10, n01 = c * m01 - sn * m11;
+        double n10 = sn * m00 + c * m10, n11 = sn * m01 + c * m11;
+        if (bi == bj && sn != 0.0) {
+          n01 = 0.0;
+          n10 = 0.0;
+        }
+        JA[p * C::JLD + p2] = n00;
+        JA[p * C::JLD + q2] = n01;
+        JA[q * C::JLD + p2] = n10;
+        JA[q * C::JLD + q2] = n11;
+      }
+      // V <- V J on the rows of the real matrix (padded rows stay unit vectors)
+      for (int u = tg; u < KK * HP; u += C::NTG) {
+        const int x = u / HP, bj = u % HP;
+        if (x < k) {
+          const int pq2 = pr[bj];
+          const int p2 = pq2 & 0xff, q2 = pq2 >> 8;
+          const double c2 = P.ROT[bj], s2 = P.ROT[C::KK / 2 + bj];
+          const double v0 = JV[x * C::JLD + p2], v1 = JV[x * C::JLD + q2];
+          JV[x * C::JLD + p2] = c2 * v0 - s2 * v1;
+          JV[x * C::JLD + q2] = s2 * v0 + c2 * v1;
+        }
+      }
+      gsync<C::NW>();
+    }
+    if (!swept) break;
+  }
+
+  // ---- eigen order, numerical rank, Ut = U_p / sqrt(sigma) -------------------------------
+  if (tg < KK) {
+    const double dx = JA[tg * C::JLD + tg];
+    int rk = 0;
+    for (int y = 0; y < KK; ++y) {
+      const double dy = JA[y * C::JLD + y];
+      rk += (dy > dx) || (dy == dx && y < tg);
+    }
+    P.ord[rk] = tg;
+  }
+  gsync<C::NW>();
+  sig0 = JA[P.ord[0] * C::JLD + P.ord[0]];
+  const int plim = (int)((int64_t)(k - 1) < m ? (int64_t)(k - 1) : m);
+  // relative floor of the Gram eigenvalues: the rounding level of the accumulated moments
+  const double rtol = (double)(m > k ? m : k) * unit;
+  pe = 0;
+  if (sig0 > 0.0) {
+    while (pe < plim && JA[P.ord[pe] * C::JLD + P.ord[pe]] > rtol * sig0) ++pe;
+  }
+  for (int e = tg; e < KMAX * KMAX; e += C::NTG) {
+    const int a = e / KMAX, l = e % KMAX;
+    if (a < k && l < pe) {
+      const int x = P.ord[l];
+      P.UT[a * KMAX + l] = JV[a * C::JLD + x] / sqrt(JA[x * C::JLD + x]);
+    }
+  }
+  gsync<C::NW>();
+}
+
 // Moment precision of patch_front: float32 MFMA, bf16 MFMA (float32 Gram), float64 MFMA.
 constexpr int MOM_FP32 = 0;
 constexpr int MOM_BF16 = 1;
@@ -451,128 +579,17 @@ __device__ uint8_t patch_front(const PointLds& P, const float* __restrict__ X, i
   tauk = P.RED[15 * C::NW];
   if (misc[1]) return PF_NONFINITE;
 
-  // ---- k x k eigen-solve: cyclic Jacobi, parallel (round-robin) order, float64 -------
-  // The matrix is padded to KK = KMAX (even) with zero rows and columns, which never
-  // rotate, so every loop bound is a compile-time constant.  Each round rotates KK/2
-  // disjoint planes; the update works on 2 x 2 blocks of A (pair i x pair i') and on row x
-  // of V restricted to one pair, so every thread reads and writes the same cells and the
-  // update runs in place.  A round whose planes are all below threshold skips its update.
-  constexpr int KK = C::KK;
-  constexpr int HP = KK / 2;
-  const MomT<PREC>* Krow = mom + (k + 1) * C::NPAD;
-  double trace = 0.0;
-  for (int e = tg; e < KK * KK; e += C::NTG) {
-    const int x = e / KK, y = e % KK;
-    JA[x * C::JLD + y] = (x < k && y < k) ? (double)Krow[P.PIDX[x * KMAX + y]] : 0.0;
-    JV[x * C::JLD + y] = (x == y) ? 1.0 : 0.0;
-  }
-  for (int e = tg; e < (KK - 1) * HP; e += C::NTG) {
-    const int r = e / HP, i = e % HP;
-    const int pa = rr_player(i, r, KK), pb = rr_player(KK - 1 - i, r, KK);
-    P.pairs[e] = (uint16_t)((pa < pb ? pa : pb) | ((pa < pb ? pb : pa) << 8));
-  }
-  for (int x = 0; x < k; ++x) trace += (double)Krow[P.PIDX[x * KMAX + x]];
-  gsync<C::NW>();
-  const double floor_abs = trace * 0x1p-100;
-  sweep = 0;
-  for (; sweep < JAC_MAX_SWEEPS; ++sweep) {
-    int swept = 0;
-    for (int r = 0; r < KK - 1; ++r) {
-      const uint16_t* pr = P.pairs + r * HP;
-      int rot = 0;
-      if (tg < HP) {
-        const int pq = pr[tg];
-        const int p = pq & 0xff, q = pq >> 8;
-        const double app = JA[p * C::JLD + p], aqq = JA[q * C::JLD + q], apq = JA[p * C::JLD + q];
-        double c = 1.0, sn = 0.0;
-        const double thr = fmax(0x1p-52 * sqrt(fabs(app) * fabs(aqq)), floor_abs);
-        if (fabs(apq) > thr) {
-          // t = tan(phi), the smaller root of t^2 + 2 t (aqq - app)/(2 apq) - 1 = 0
-          const double d = aqq - app, e2 = 2.0 * apq;
-          const double t0 = e2 / (fabs(d) + sqrt(fma(d, d, e2 * e2)));
-          const double t = d < 0.0 ? -t0 : t0;
-          c = rsqrt_nr(fma(t, t, 1.0));
-          sn = t * c;
-          rot = 1;
-        }
-        P.ROT[tg] = c;
-        P.ROT[C::KK / 2 + tg] = sn;
-      }
-      rot = __any(rot);                   // the rotating lanes all sit in wave 0
-      if constexpr (C::NW > 1) {
-        if (tg == 0) misc[3 + (r & 1)] = rot;   // two slots: a skipped round has no second barrier
-      }
-      gsync<C::NW>();
-      if constexpr (C::NW > 1) rot = misc[3 + (r & 1)];
-      if (!rot) continue;                 // nothing rotates in this round
-      swept = 1;
-      // A <- J^T A J on 2 x 2 blocks
-      for (int u = tg; u < HP * HP; u += C::NTG) {
-        const int bi = u / HP, bj = u % HP;
-        const int pq1 = pr[bi], pq2 = pr[bj];
-        const int p = pq1 & 0xff, q = pq1 >> 8, p2 = pq2 & 0xff, q2 = pq2 >> 8;
-        const double c = P.ROT[bi], sn = P.ROT[C::KK / 2 + bi];
-        const double c2 = P.ROT[bj], s2 = P.ROT[C::KK / 2 + bj];
-        const double a00 = JA[p * C::JLD + p2], a01 = JA[p * C::JLD + q2];
-        const double a10 = JA[q * C::JLD + p2], a11 = JA[q * C::JLD + q2];
-        // columns: (p2, q2) <- (c2 a_p2 - s2 a_q2, s2 a_p2 + c2 a_q2)
-        const double m00 = c2 * a00 - s2 * a01, m01 = s2 * a00 + c2 * a01;
-        const double m10 = c2 * a10 - s2 * a11, m11 = s2 * a10 + c2 * a11;
-        // rows: (p, q) <- (c m_p - s m_q, s m_p + c m_q)
-        double n00 = c * m00 - sn * m10, n01 = c * m01 - sn * m11;
-        double n10 = sn * m00 + c * m10, n11 = sn * m01 + c * m11;
-        if (bi == bj && sn != 0.0) {
-          n01 = 0.0;
-          n10 = 0.0;
-        }
-        JA[p * C::JLD + p2] = n00;
-        JA[p * C::JLD + q2] = n01;
-        JA[q * C::JLD + p2] = n10;
-        JA[q * C::JLD + q2] = n11;
-      }
-      // V <- V J on the rows of the real matrix (padded rows stay unit vectors)
-      for (int u = tg; u < KK * HP; u += C::NTG) {
-        const int x = u / HP, bj = u % HP;
-        if (x < k) {
-          const int pq2 = pr[bj];
-          const int p2 = pq2 & 0xff, q2 = pq2 >> 8;
-          const double c2 = P.ROT[bj], s2 = P.ROT[C::KK / 2 + bj];
-          const double v0 = JV[x * C::JLD + p2], v1 = JV[x * C::JLD + q2];
-          JV[x * C::JLD + p2] = c2 * v0 - s2 * v1;
-          JV[x * C::JLD + q2] = s2 * v0 + c2 * v1;
-        }
-      }
-      gsync<C::NW>();
-    }
-    if (!swept) break;
-  }
-
-  // ---- eigen order, numerical rank, Ut = U_p / sqrt(sigma) -------------------------------
-  if (tg < KK) {
-    const double dx = JA[tg * C::JLD + tg];
-    int rk = 0;
-    for (int y = 0; y < KK; ++y) {
-      const double dy = JA[y * C::JLD + y];
-      rk += (dy > dx) || (dy == dx && y < tg);
-    }
-    P.ord[rk] = tg;
-  }
-  gsync<C::NW>();
-  sig0 = JA[P.ord[0] * C::JLD + P.ord[0]];
-  const int plim = (int)((int64_t)(k - 1) < m ? (int64_t)(k - 1) : m);
-  // relative floor of the Gram eigenvalues: the rounding level of the accumulated moments
-  const double rtol = (double)(m > k ? m : k) * (PREC == MOM_FP64 ? 0x1p-44 : 0x1p-24);
-  pe = 0;
-  if (sig0 > 0.0) {
-    while (pe < plim && JA[P.ord[pe] * C::JLD + P.ord[pe]] > rtol * sig0) ++pe;
-  }
-  for (int e = tg; e < KMAX * KMAX; e += C::NTG) {
-    const int a = e / KMAX, l = e % KMAX;
-    if (a < k && l < pe) {
-      const int x = P.ord[l];
-      P.UT[a * KMAX + l] = JV[a * C::JLD + x] / sqrt(JA[x * C::JLD + x]);
+  // ---- k x k eigen-solve (float64 Jacobi) on K ---------------------------------------
+  {
+    constexpr int KK = C::KK;
+    const MomT<PREC>* Krow = mom + (k + 1) * C::NPAD;
+    for (int e = tg; e < KK * KK; e += C::NTG) {
+      const int x = e / KK, y = e % KK;
+      JA[x * C::JLD + y] = (x < k && y < k) ? (double)Krow[P.PIDX[x * KMAX + y]] : 0.0;
+      JV[x * C::JLD + y] = (x == y) ? 1.0 : 0.0;
     }
   }
+  jacobi_eigen<KMAX, C>(P, k, m, tg, PREC == MOM_FP64 ? 0x1p-44 : 0x1p-24, sig0, pe, sweep);
   gsync<C::NW>();
   return 0;
 }

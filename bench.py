@@ -210,6 +210,56 @@ def suite(args):
         torch.cuda.empty_cache()
 
 
+def sweep(args):
+    """Fast-vs-exact agreement against m/k on synthetic manifolds: one JSON line per case with
+    the relative error of both Fast readings against the exact value (canonical basis), the
+    paper's three agreement criteria, and on a small sample the oracle's exact value with the
+    LAPACK eigenbasis (the Exact branch as printed) against the canonical one."""
+    import numpy as np
+    import torch
+
+    import paper_2606_06329_amd as P
+    from oracle import curvature as oc
+    from paper_2606_06329_amd import metrics, synth
+
+    n = 2000
+    cases = [("torus", m, 8) for m in (16, 32, 64, 128, 256, 512, 800)]
+    cases += [("swissroll", m, 8) for m in (16, 64, 256, 800)]
+    cases += [("torus", m, 16) for m in (32, 128, 512, 1000)]
+    for name, m, k in cases:
+        if not P.exact_supported(m, k):
+            continue
+        X = synth.WORKLOADS[name][0](n=n, m=m, seed=7000 + m + k)
+        Xd = torch.from_numpy(X).cuda()
+        idx, _, kfl = P.knn(Xd, k)
+        ex, efl = P.curvature_exact(Xd, idx)
+        line = {"sweep": name, "n": n, "m": m, "k": k, "m_over_k": round(m / k, 2)}
+        ex_np = ex.cpu().numpy().astype(np.float64)
+        ok = ((efl | kfl).cpu().numpy() & 0x0E) == 0        # no degenerate / rank / sweep flags
+        for variant in ("paper", "haar"):
+            fa, _ = P.curvature_fast(Xd, idx, variant)
+            fa = fa.cpu().numpy().astype(np.float64)
+            rel = np.abs(fa - ex_np)[ok] / ex_np[ok]
+            ag = metrics.agreement(ex_np[ok], fa[ok])
+            line[variant] = {"median_rel": float(np.median(rel)), "p90_rel": float(np.quantile(rel, 0.9)),
+                             "mae": ag["mae"], "spearman": ag["spearman"], "xi": ag["xi"]}
+        # the printed Exact branch (LAPACK eigenbasis of the m x m covariance) on a sample
+        X64 = X.astype(np.float64)
+        idx_np = idx.cpu().numpy()
+        rows = [i for i in range(0, n, n // 40) if ok[i]][:30]
+        lap = np.array([oc.lapack_exact_kappa(oc.patch(X64, idx_np[i])) for i in rows])
+        line["lapack_vs_canonical_median_rel"] = float(np.median(np.abs(lap - ex_np[rows]) / ex_np[rows]))
+        for variant in ("paper", "haar"):
+            fa, _ = P.curvature_fast(Xd, idx, variant)
+            fa = fa.cpu().numpy().astype(np.float64)[rows]
+            rel = np.abs(fa - lap) / lap
+            line[variant]["vs_lapack_median_rel"] = float(np.median(rel))
+            line[variant]["vs_lapack_max_rel"] = float(np.max(rel))
+        line["points"] = int(ok.sum())
+        print(json.dumps(line), flush=True)
+        del Xd
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,6 +273,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the secondary measurements (other precisions, exact mode)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the headline line, the Fast-vs-exact agreement sweep over m/k")
     ap.add_argument("--suite", action="store_true",
                     help="instead of the headline line, one line per secondary configuration")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -235,6 +287,9 @@ def main():
 
     if args.suite:
         suite(args)
+        return
+    if args.sweep:
+        sweep(args)
         return
 
     import numpy as np

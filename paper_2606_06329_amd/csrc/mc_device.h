@@ -42,12 +42,9 @@ __device__ __forceinline__ float wave_max(float v) {
   return v;
 }
 
-// Round-to-nearest-even float -> bfloat16 bits (finite inputs).
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
+// Round-to-nearest-even float -> bfloat16 bits (gfx950 converts in hardware, two values
+// per v_cvt_pk_bf16_f32 when adjacent conversions pair up).
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 

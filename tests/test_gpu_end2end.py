@@ -48,3 +48,37 @@ def test_full_size_sampled(name):
     # property at every point: kappa finite and non-negative
     assert np.all(np.isfinite(kap)) and np.all(kap >= 0)
     print(f"  uncertified {(fl & 32).astype(bool).mean():.4f}, rank-deficient {(fl & 4).astype(bool).mean():.4f}")
+
+
+@pytest.mark.parametrize("precision,tol,noise", [("fp64", None, 0.05), ("fp32", 1e-3, 0.3)])
+def test_very_large_m_auto_mode(precision, tol, noise):
+    """The paper's widest regime (n = 283, m = 54621, like its largest expression array):
+    Auto mode picks the Fast branch (m >= 50), the kernels stream m in chunks, and every
+    point matches the oracle; k is the default floor(log2 n).  float64 moments hold the
+    float64 bar; float32 moments summed over 54621 columns carry about sqrt(m) 2^-24 = 1.4e-5
+    relative error into the Gram matrix, so their bar is 1e-3, and their rank test (eigenvalues
+    above m 2^-24 sigma_1) needs the noise directions of the patch to stay above 3e-3."""
+    import paper_2606_06329_amd as P
+    from tests.gpu_common import TOL_FP64
+    tol = TOL_FP64 if tol is None else tol
+    rng = np.random.default_rng(54621)
+    n, m = 283, 54621
+    # a curved 3-dimensional chart with noise, as float32
+    z = rng.standard_normal((n, 3))
+    A = rng.standard_normal((3, m)) / np.sqrt(3)
+    B = rng.standard_normal((6, m)) / 6.0
+    quad = np.stack([z[:, 0] ** 2, z[:, 1] ** 2, z[:, 2] ** 2, z[:, 0] * z[:, 1], z[:, 0] * z[:, 2],
+                     z[:, 1] * z[:, 2]], axis=1)
+    X = (z @ A + quad @ B + noise * rng.standard_normal((n, m))).astype(np.float32)
+    k = P.default_k(n)
+    print(f"very large m: n={n} m={m} k={k} {precision}", flush=True)
+    kap, idx, fl = P.curvature(to_dev(X), mode="auto", precision=precision)
+    idx = idx.cpu().numpy()
+    bad_big, _, _, _ = knn_set_report(idx, X, np.arange(0, n, 7), k)
+    assert bad_big == 0
+    want, pe = oracle_fast(X, idx, "paper")
+    ok_rows = ((fl.cpu().numpy() & 4) == 0) & (pe == k - 1)
+    err = rel_err(kap.cpu().numpy(), want)[ok_rows]
+    print(f"  rank-full points {ok_rows.sum()}, max rel err {err.max():.2e}", flush=True)
+    assert ok_rows.mean() > 0.95
+    assert err.max() <= tol

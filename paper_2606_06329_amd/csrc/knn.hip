@@ -683,16 +683,47 @@ __global__ __launch_bounds__(256) void knn_rerank_kernel(
 #pragma unroll
   for (int r = 0; r < KCMAX; ++r) acc[r] = 0.0f;
   const float* xq = X + qi * ldx;
-  for (int64_t c0 = 0; c0 < m; c0 += WAVE) {
-    const int64_t c = c0 + lane;
-    const bool in = c < m;
-    const float xv = in ? xq[c] : 0.0f;
+  if ((ldx & 3) == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0) {
+    // 16-byte rows: each lane reads four consecutive columns per candidate row
+    for (int64_t c0 = 0; c0 < m; c0 += 4 * WAVE) {
+      const int64_t c = c0 + 4 * lane;
+      float4 xv = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (c + 3 < m) {
+        xv = *reinterpret_cast<const float4*>(xq + c);
+      } else if (c < m) {
+        xv.x = xq[c];
+        if (c + 1 < m) xv.y = xq[c + 1];
+        if (c + 2 < m) xv.z = xq[c + 2];
+      }
 #pragma unroll
-    for (int r = 0; r < KCMAX; ++r) {
-      if (r < kc) {
-        const int j = __builtin_amdgcn_readlane(jsafe, r);
-        const float df = xv - (in ? X[(int64_t)j * ldx + c] : 0.0f);
-        acc[r] = fmaf(df, df, acc[r]);
+      for (int r = 0; r < KCMAX; ++r) {
+        if (r < kc) {
+          const float* yr = X + (int64_t)__builtin_amdgcn_readlane(jsafe, r) * ldx;
+          float4 yv = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (c + 3 < m) {
+            yv = *reinterpret_cast<const float4*>(yr + c);
+          } else if (c < m) {
+            yv.x = yr[c];
+            if (c + 1 < m) yv.y = yr[c + 1];
+            if (c + 2 < m) yv.z = yr[c + 2];
+          }
+          const float d0 = xv.x - yv.x, d1 = xv.y - yv.y, d2 = xv.z - yv.z, d3 = xv.w - yv.w;
+          acc[r] = fmaf(d3, d3, fmaf(d2, d2, fmaf(d1, d1, fmaf(d0, d0, acc[r]))));
+        }
+      }
+    }
+  } else {
+    for (int64_t c0 = 0; c0 < m; c0 += WAVE) {
+      const int64_t c = c0 + lane;
+      const bool in = c < m;
+      const float xv = in ? xq[c] : 0.0f;
+#pragma unroll
+      for (int r = 0; r < KCMAX; ++r) {
+        if (r < kc) {
+          const int j = __builtin_amdgcn_readlane(jsafe, r);
+          const float df = xv - (in ? X[(int64_t)j * ldx + c] : 0.0f);
+          acc[r] = fmaf(df, df, acc[r]);
+        }
       }
     }
   }

@@ -51,13 +51,25 @@ __global__ __launch_bounds__(256) void knn_colsum_kernel(const float* __restrict
   part[(int64_t)blockIdx.y * m + c] = s;
 }
 
+// Column means from the partial sums: a block takes 16 columns, its 256 threads take 16
+// partial sums each (16 groups), then the groups are added in a fixed order (deterministic).
 __global__ __launch_bounds__(256) void knn_mean_kernel(const double* __restrict__ part, int64_t m,
                                                        int nparts, int64_t n, float* __restrict__ mu) {
-  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (c >= m) return;
+  __shared__ double red[16][17];
+  const int cl = threadIdx.x % 16, grp = threadIdx.x / 16;
+  const int64_t c = (int64_t)blockIdx.x * 16 + cl;
   double s = 0.0;
-  for (int p = 0; p < nparts; ++p) s += part[(int64_t)p * m + c];
-  mu[c] = (float)(s / (double)n);
+  if (c < m) {
+    for (int p = grp; p < nparts; p += 16) s += part[(int64_t)p * m + c];
+  }
+  red[grp][cl] = s;
+  __syncthreads();
+  if (grp == 0 && c < m) {
+    double t = 0.0;
+#pragma unroll
+    for (int g = 0; g < 16; ++g) t += red[g][cl];
+    mu[c] = (float)(t / (double)n);
+  }
 }
 
 // One wave per row: the centred row xc = fl(x - mu) in the GEMM's input format (float32,
@@ -860,7 +872,8 @@ hipError_t launch_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int k, 
                      ldx, rows_per, part);
   timing_end(0, stream);
   timing_begin(1, stream);
-  hipLaunchKernelGGL(knn_mean_kernel, dim3(gx), dim3(256), 0, stream, part, m, (int)parts, n, mu);
+  hipLaunchKernelGGL(knn_mean_kernel, dim3((unsigned)((m + 15) / 16)), dim3(256), 0, stream, part, m,
+                     (int)parts, n, mu);
   timing_end(1, stream);
   timing_begin(2, stream);
   hipLaunchKernelGGL(knn_center_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream, X, n,

@@ -97,7 +97,10 @@ extern "C" {
  * K' = rerank_factor * k candidates per point; they are re-ranked with float32
  * difference-form distances sum_a (x_a - y_a)^2 on the original X and the k
  * smallest are kept, ordered by (distance, index).  With rerank_factor == 1 the
- * GEMM distances decide (MC_FP32 only).
+ * GEMM distances decide (MC_FP32 only).  The distance matrix is symmetric: while
+ * the workspace for it stays within 8 GiB (n up to 65536), each unordered pair
+ * of 128-point tiles is scored once and its transposed 64 KiB score tile serves
+ * the other tile's queries, so the workspace then holds about n^2 / 2 floats.
  *
  *   X            [n x ldx] float32, device
  *   n, m, ldx    points, dimensions, row stride (elements)
@@ -197,7 +200,8 @@ int mc_curvature_backward(const float* X, int64_t n, int64_t m, int64_t ldx, con
 #define MC_STAGE_CURV_FAST 6
 #define MC_STAGE_CURV_EXACT 7
 #define MC_STAGE_CURV_BACKWARD 8
-#define MC_STAGE_COUNT 9
+#define MC_STAGE_KNN_COLUMN_TOPK 9
+#define MC_STAGE_COUNT 10
 int mc_timing_enable(int on);
 int mc_timing_read(int32_t stage, double* total_ms, int64_t* launches);
 const char* mc_stage_name(int32_t stage);

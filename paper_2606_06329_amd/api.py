@@ -56,6 +56,18 @@ def default_rerank(k: int, n: int, precision: str = "fp32") -> int:
     return r
 
 
+# the library's workspace limit for the symmetric tile-pair schedule (one 64 KiB transposed
+# score tile per unordered pair of 128-point tiles)
+KNN_SYM_MAX_BYTES = 8 << 30
+
+
+def knn_symmetric(n: int) -> bool:
+    """Whether mc_knn scores each unordered pair of 128-point tiles once (n up to about 65536)
+    rather than every ordered pair: its distance GEMM then does n (n + 1) m flop, not 2 n^2 m."""
+    T = -(-int(n) // 128)
+    return T >= 2 and (T * (T - 1) // 2) * 65536 <= KNN_SYM_MAX_BYTES
+
+
 def knn(X: torch.Tensor, k: int, precision: str = "fp32", rerank: int | None = None,
         include_self: bool = False, strict: bool = False, ws: torch.Tensor | None = None):
     """k nearest neighbours of every row of X (Step 1): (idx int32 n x k, d2 float32 n x k, flags uint8 n).

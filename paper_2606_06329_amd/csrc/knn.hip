@@ -243,9 +243,13 @@ __device__ __forceinline__ void wave_merge64(uint32_t& hi, uint32_t& lo, uint32_
 
 constexpr int INSERT_MAX = 12;   // up to this many survivors go in one by one; more: sort + merge
 
-// Filter 64 candidate keys (one per lane) against the row list and take in what passes.
-__device__ __forceinline__ void half_update(uint32_t& hi, uint32_t& lo, uint32_t vh, uint32_t vl, int kc) {
-  uint32_t th = rdlane_u(hi, kc - 1);
+__device__ __forceinline__ uint32_t umin32(uint32_t a, uint32_t b) { return a < b ? a : b; }
+
+// Filter 64 candidate keys (one per lane) against the row list (and below `cap`) and take
+// in what passes.
+__device__ __forceinline__ void half_update(uint32_t& hi, uint32_t& lo, uint32_t vh, uint32_t vl, int kc,
+                                            uint32_t cap) {
+  uint32_t th = umin32(rdlane_u(hi, kc - 1), cap);
   uint64_t msk = __ballot(vh < th);
   if (!msk) return;
   if (__popcll(msk) <= INSERT_MAX) {
@@ -255,7 +259,7 @@ __device__ __forceinline__ void half_update(uint32_t& hi, uint32_t& lo, uint32_t
       const uint32_t sh = rdlane_u(vh, src);
       if (sh < th) {
         list_insert(hi, lo, sh, rdlane_u(vl, src));
-        th = rdlane_u(hi, kc - 1);
+        th = umin32(rdlane_u(hi, kc - 1), cap);
       }
     }
   } else {
@@ -266,12 +270,13 @@ __device__ __forceinline__ void half_update(uint32_t& hi, uint32_t& lo, uint32_t
   }
 }
 
-// Take in the survivors of a row's 128 candidates (two 64-lane halves).  Few survivors go
-// in one by one; up to 64 are packed into one vector (forward permute), sorted and merged
-// once; more than 64 (early tiles) fall back to one sort + merge per half.
+// Take in the survivors of a row's 128 candidates (two 64-lane halves): keys below both the
+// list's K'-th key and `cap`.  Few survivors go in one by one; up to 64 are packed into one
+// vector (forward permute), sorted and merged once; more than 64 (early tiles) fall back to
+// one sort + merge per half.
 __device__ __forceinline__ void row_update(uint32_t& hi, uint32_t& lo, uint32_t vh0, uint32_t vl0,
-                                           uint32_t vh1, uint32_t vl1, int kc) {
-  uint32_t th = rdlane_u(hi, kc - 1);
+                                           uint32_t vh1, uint32_t vl1, int kc, uint32_t cap) {
+  uint32_t th = umin32(rdlane_u(hi, kc - 1), cap);
   const uint64_t m0 = __ballot(vh0 < th), m1 = __ballot(vh1 < th);
   const int c0 = __popcll(m0), c = c0 + __popcll(m1);
   if (c == 0) return;
@@ -286,7 +291,7 @@ __device__ __forceinline__ void row_update(uint32_t& hi, uint32_t& lo, uint32_t 
         const uint32_t sh = rdlane_u(vh, src);
         if (sh < th) {
           list_insert(hi, lo, sh, rdlane_u(vl, src));
-          th = rdlane_u(hi, kc - 1);
+          th = umin32(rdlane_u(hi, kc - 1), cap);
         }
       }
     }
@@ -307,21 +312,22 @@ __device__ __forceinline__ void row_update(uint32_t& hi, uint32_t& lo, uint32_t 
     wave_sort64<false>(bh, bl);
     wave_merge64(hi, lo, bh, bl);
   } else {
-    half_update(hi, lo, vh0, vl0, kc);
-    half_update(hi, lo, vh1, vl1, kc);
+    half_update(hi, lo, vh0, vl0, kc, cap);
+    half_update(hi, lo, vh1, vl1, kc, cap);
   }
 }
 
 // ------------------------------------------------------------------------------------
-// GEMM + top-K'.  PREC 0: fp32 MFMA 32x32x2, BK = 16; PREC 1: bf16 MFMA 16x16x32, BK = 64.
+// GEMM + top-K'.  PREC 0: fp32 MFMA 32x32x2, BK = 16; PREC 1: bf16 MFMA 16x16x32, BK = 64;
+// PREC 2: fp8 e4m3 MFMA 16x16x32 with per-row scales.
 //
-// Work is the grid of (query tile, database tile) pairs, P = QT * NT, in query-major
-// order.  Workgroup L takes the contiguous range [L*P/G, (L+1)*P/G): every workgroup
-// does the same amount of MFMA work, a query tile is cut into at most a few
-// segments (each refills its lists once), and because G >= QT a range touches at
-// most two query tiles.  Workgroups are dispatched round-robin over the 8 XCDs, so
-// the logical id is remapped to give each XCD a block of consecutive ranges: its
-// workgroups then share query tiles in their own L2.
+// Work is a list of (query tile, database tile) pairs in query-major order (the tile-pair
+// schedules below).  Workgroup L takes the contiguous range [L*P/G, (L+1)*P/G): every
+// workgroup does the same amount of MFMA work, a query tile is cut into at most a few
+// segments (each refills its lists once), and because G >= the tile count a range touches
+// at most two query tiles.  Workgroups are dispatched round-robin over the 8 XCDs, so the
+// logical id is remapped to give each XCD a block of consecutive ranges: its workgroups
+// then share query tiles in their own L2.
 // ------------------------------------------------------------------------------------
 template <int PREC>
 struct GemmCfg;
@@ -400,7 +406,97 @@ __host__ __device__ __forceinline__ int64_t range_owner(int64_t t, int64_t G, in
   return ((t + 1) * G - 1) / P;
 }
 
-// Scores s[i][j] = ||y_j||^2 - 2 x_i . y_j of one 128 x 128 tile into Ss (LDS).
+// Tile-pair schedules.  Pairs are numbered row tile by row tile: row tile i owns a_len(i)
+// consecutive pairs from a_start(i), pair (i, d) scoring query tile i against database
+// tile a_db(i, d).
+//  * full (sym = 0): every row tile meets all T tiles, d = 0 .. T-1.
+//  * symmetric (sym = 1): the score matrix is symmetric, so each unordered tile pair is
+//    scored once.  Row tile i meets the tiles (i + d) mod T, d = 0 .. h (plus d = T/2 for
+//    i < T/2 when T is even): the circulant half of the pairs, about T/2 per row tile.
+//    The transposed tile of every off-diagonal pair serves the queries of its database
+//    tile (the column side); column tile j receives the pairs ((j - d) mod T, j),
+//    d = 1 .. b_len(j), numbered column tile by column tile from b_start(j).
+struct TileSched {
+  int64_t T;   // 128-point tiles
+  int64_t h;   // off-diagonal pairs of every row tile in the symmetric schedule, (T - 1) / 2
+  int64_t e;   // row tiles with one more (T even: T / 2, else 0)
+  int sym;
+};
+
+__host__ __device__ __forceinline__ TileSched make_sched(int64_t n, int sym) {
+  TileSched s;
+  s.T = (n + KBQ - 1) / KBQ;
+  s.h = (s.T - 1) / 2;
+  s.e = (s.T % 2 == 0) ? s.T / 2 : 0;
+  s.sym = sym;
+  return s;
+}
+__host__ __device__ __forceinline__ int64_t a_len(const TileSched& s, int64_t i) {
+  return s.sym ? s.h + 1 + (i < s.e ? 1 : 0) : s.T;
+}
+__host__ __device__ __forceinline__ int64_t a_start(const TileSched& s, int64_t i) {
+  return s.sym ? i * (s.h + 1) + (i < s.e ? i : s.e) : i * s.T;
+}
+__host__ __device__ __forceinline__ int64_t a_pairs(const TileSched& s) {
+  return s.sym ? s.T * (s.h + 1) + s.e : s.T * s.T;
+}
+__host__ __device__ __forceinline__ void a_pair(const TileSched& s, int64_t t, int64_t& i, int64_t& d) {
+  if (!s.sym) {
+    i = t / s.T;
+    d = t % s.T;
+    return;
+  }
+  const int64_t lead = s.e * (s.h + 2);   // the e row tiles of h + 2 pairs come first
+  if (t < lead) {
+    i = t / (s.h + 2);
+    d = t % (s.h + 2);
+  } else {
+    const int64_t u = t - lead;
+    i = s.e + u / (s.h + 1);
+    d = u % (s.h + 1);
+  }
+}
+__host__ __device__ __forceinline__ int64_t a_db(const TileSched& s, int64_t i, int64_t d) {
+  return s.sym ? (i + d >= s.T ? i + d - s.T : i + d) : d;   // d < T
+}
+// the pair after (i, d) in schedule order
+__host__ __device__ __forceinline__ void a_next(const TileSched& s, int64_t& i, int64_t& d) {
+  if (++d == a_len(s, i)) {
+    ++i;
+    d = 0;
+  }
+}
+__host__ __device__ __forceinline__ int64_t b_len(const TileSched& s, int64_t j) {
+  return s.h + (j >= s.T - s.e ? 1 : 0);
+}
+__host__ __device__ __forceinline__ int64_t b_start(const TileSched& s, int64_t j) {
+  return j * s.h + (j > s.T - s.e ? j - (s.T - s.e) : 0);
+}
+__host__ __device__ __forceinline__ int64_t b_pairs(const TileSched& s) { return s.T * s.h + s.e; }
+__host__ __device__ __forceinline__ void b_pair(const TileSched& s, int64_t t, int64_t& j, int64_t& d) {
+  const int64_t lead = (s.T - s.e) * s.h;   // column tiles with h pairs come first
+  if (t < lead) {
+    j = t / s.h;
+    d = 1 + t % s.h;
+  } else {
+    const int64_t u = t - lead;
+    j = (s.T - s.e) + u / (s.h + 1);
+    d = 1 + u % (s.h + 1);
+  }
+}
+// column-side number (and transposed-tile slot) of the off-diagonal pair (i, d), d >= 1
+__host__ __device__ __forceinline__ int64_t b_index(const TileSched& s, int64_t i, int64_t d) {
+  return b_start(s, a_db(s, i, d)) + d - 1;
+}
+// list segments of one row (column) tile: workgroups whose ranges meet [first, first + len)
+__host__ __device__ __forceinline__ int64_t segments(int64_t first, int64_t len, int64_t G, int64_t P) {
+  return len > 0 ? range_owner(first + len - 1, G, P) - range_owner(first, G, P) + 1 : 0;
+}
+
+// Cross terms D[i][j] = -2 x_i . y_j of one 128 x 128 tile into Ss (LDS); +inf past column n
+// and, unless include_self, on the diagonal.  The score of y_j for query x_i is then
+// ||y_j||^2 + D[i][j] and that of x_i for query y_j is ||x_i||^2 + D[i][j]; for the float32
+// and bf16 copies each equals the fused fmaf(-2, dot, norm), as -2 dot is exact.
 // 8 waves as 2 (query rows) x 4 (db columns); wave tile 64 x 32.  On entry `pre` holds
 // stage 0 of this tile (the caller loads it early, behind the previous tile's top-K').
 template <int PREC>
@@ -456,13 +552,12 @@ __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64
     const int64_t gj = j0 + col;
     const bool colok = gj < n;
     const int dq = (int)(j0 - q0) + col;   // column index relative to the query tile (int32)
-    const float nj = colok ? norms[gj] : 0.0f;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int row = 64 * wr + 32 * a + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
-        float sc = fmaf(-2.0f, acc[a][r], nj);
+        float sc = -2.0f * acc[a][r];
         if (!colok || (!include_self && dq == row)) sc = INFINITY;
         Ss[row * SLD + col] = sc;
       }
@@ -503,13 +598,12 @@ __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64
       const int64_t gj = j0 + col;
       const bool colok = gj < n;
       const int dq = (int)(j0 - q0) + col;
-      const float nj = colok ? norms[gj] : 0.0f;
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = 64 * wr + 16 * a + 4 * (lane / 16) + r;
-          float sc = fmaf(-2.0f, acc[a][b][r], nj);
+          float sc = -2.0f * acc[a][b][r];
           if (!colok || (!include_self && dq == row)) sc = INFINITY;
           Ss[row * SLD + col] = sc;
         }
@@ -553,7 +647,6 @@ __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64
       const int64_t gj = j0 + col;
       const bool colok = gj < n;
       const int dq = (int)(j0 - q0) + col;
-      const float nj = colok ? norms[gj] : 0.0f;
       const float sj = colok ? scales[gj] : 0.0f;
       const float* sq = scales + q0;                // row scales of the query tile
       const int nq = (int)(n - q0 < KBQ ? n - q0 : KBQ);
@@ -563,7 +656,7 @@ __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64
         for (int r = 0; r < 4; ++r) {
           const int row = 64 * wr + 16 * a + 4 * (lane / 16) + r;
           const float si = row < nq ? sq[row] : 0.0f;
-          float sc = fmaf(-2.0f * si * sj, acc[a][b][r], nj);
+          float sc = (-2.0f * si * sj) * acc[a][b][r];
           if (!colok || (!include_self && dq == row)) sc = INFINITY;
           Ss[row * SLD + col] = sc;
         }
@@ -571,17 +664,67 @@ __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64
   }
 }
 
+// Top-K' update of the RPW rows a wave owns against 128 new candidates c0 .. c0 + 127, in
+// two steps.  lists_filter: a cheap, unrolled pass marks the rows with any score below
+// their threshold (the list's K'-th key and cap[rr], the caller's upper bound for row rr);
+// score(rr, h) is row rr's score of candidate c0 + 64 h + lane, rr a compile-time index.
+// lists_apply: only the marked rows are swapped into working registers and updated (one
+// copy of the code); score(rr, h) is read again with rr a run-time index.
+template <class F>
+__device__ __forceinline__ uint32_t lists_filter(const uint32_t (&lh)[RPW], const F& score, int kc,
+                                                 const uint32_t (&cap)[RPW]) {
+  uint32_t need = 0;
+#pragma unroll
+  for (int rr = 0; rr < RPW; ++rr) {
+    const uint32_t own = rdlane_u(lh[rr], kc - 1);
+    const uint32_t th = own < cap[rr] ? own : cap[rr];
+    // no short-circuit: every score load is issued up front
+    const bool hit = (f2ord(score(rr, 0)) < th) | (f2ord(score(rr, 1)) < th);
+    need |= (__ballot(hit) != 0ull ? 1u : 0u) << rr;
+  }
+  return need;
+}
+
+template <class F>
+__device__ __forceinline__ void lists_apply(uint32_t (&lh)[RPW], uint32_t (&ll)[RPW], uint32_t need,
+                                            const F& score, uint32_t c0, int kc, int lane,
+                                            const uint32_t (&cap)[RPW]) {
+  while (need) {
+    const int rr = __ffs(need) - 1;
+    need &= need - 1;
+    uint32_t wh = lh[0], wl = ll[0], cp = cap[0];
+#pragma unroll
+    for (int r = 1; r < RPW; ++r) {
+      wh = rr == r ? lh[r] : wh;
+      wl = rr == r ? ll[r] : wl;
+      cp = rr == r ? cap[r] : cp;
+    }
+    row_update(wh, wl, f2ord(score(rr, 0)), c0 + (uint32_t)lane, f2ord(score(rr, 1)),
+               c0 + 64u + (uint32_t)lane, kc, cp);
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      lh[r] = rr == r ? wh : lh[r];
+      ll[r] = rr == r ? wl : ll[r];
+    }
+  }
+}
+
+// Distance GEMM + per-row top-K' over the row side of a tile-pair schedule, cut into G
+// equal ranges of pairs.  Each workgroup keeps the lists of the current row tile's 128
+// queries in registers (wave w: rows RPW w .. RPW w + RPW - 1) and writes them to list
+// slot (its rank among the workgroups sharing that row tile) when the row tile changes.
+// Under the symmetric schedule every off-diagonal pair also leaves its transposed tile in
+// tbuf for the column pass.
 template <int PREC>
 __global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) void knn_gemm_topk_kernel(
     const void* __restrict__ xsrc, int64_t mp, const float* __restrict__ norms,
-    const float* __restrict__ scales, int64_t n, int kc, int64_t G, int smax, int include_self,
-    float* __restrict__ cand_s, int* __restrict__ cand_j) {
+    const float* __restrict__ scales, int64_t n, int kc, int sym, int64_t G, int nslot,
+    int include_self, float* __restrict__ cand_s, int* __restrict__ cand_j, float* __restrict__ tbuf) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
   const int w = tid / WAVE, lane = tid % WAVE;
-  const int64_t QT = (n + KBQ - 1) / KBQ;
-  const int64_t NT = (n + KBN - 1) / KBN;
-  const int64_t P = QT * NT;
+  const TileSched S = make_sched(n, sym);
+  const int64_t P = a_pairs(S);
   // XCD-aware logical id: dispatch order bid -> XCD bid % 8
   const int64_t bid = blockIdx.x;
   const int64_t L = (G % 8 == 0) ? (bid % 8) * (G / 8) + bid / 8 : bid;
@@ -589,24 +732,30 @@ __global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
   const float* Ss = reinterpret_cast<const float*>(smem);
 
   uint32_t lh[RPW], ll[RPW];   // per-row sorted key lists (score order bits, index)
+  uint32_t nocap[RPW];
+#pragma unroll
+  for (int rr = 0; rr < RPW; ++rr) nocap[rr] = 0xFFFFFFFFu;
   int64_t cur_qt = -1;
   auto flush = [&]() {
     if (cur_qt < 0) return;
-    const int64_t seg = L - range_owner(cur_qt * NT, G, P);
+    const int64_t seg = L - range_owner(a_start(S, cur_qt), G, P);
 #pragma unroll
     for (int rr = 0; rr < RPW; ++rr) {
       const int64_t gi = cur_qt * KBQ + RPW * w + rr;
       if (gi < n && lane < kc) {
-        const int64_t o = ((cur_qt * smax + seg) * KBQ + RPW * w + rr) * kc + lane;
+        const int64_t o = ((cur_qt * nslot + seg) * KBQ + RPW * w + rr) * kc + lane;
         cand_s[o] = ord2f(lh[rr]);
         cand_j[o] = (int)ll[rr];
       }
     }
   };
+  int64_t qt = 0, d = 0;
   uint4 pre[Stage<PREC>::NPRE];
-  if (tb < te) stage_load<PREC>(pre, xsrc, mp, n, (tb / NT) * KBQ, (tb % NT) * KBN, 0);
+  if (tb < te) {
+    a_pair(S, tb, qt, d);
+    stage_load<PREC>(pre, xsrc, mp, n, qt * KBQ, a_db(S, qt, d) * KBN, 0);
+  }
   for (int64_t t = tb; t < te; ++t) {
-    const int64_t qt = t / NT, dt = t % NT;
     if (qt != cur_qt) {
       flush();
       cur_qt = qt;
@@ -616,41 +765,149 @@ __global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
         ll[rr] = KEY_PAD_LO;
       }
     }
-    const int64_t j0 = dt * KBN;
-    tile_scores<PREC>(xsrc, mp, norms, scales, n, qt * KBQ, j0, include_self, smem, pre);
+    const int64_t j0 = a_db(S, qt, d) * KBN;
+    const int64_t q0 = qt * KBQ;
+    tile_scores<PREC>(xsrc, mp, norms, scales, n, q0, j0, include_self, smem, pre);
     __syncthreads();
+    // the symmetric schedule's off-diagonal pairs leave the transposed scores for the column
+    // pass: tbuf[pair][c][r] = ||x_r||^2 + D[r][c] (+inf past row n); wave w writes columns
+    // 16 w .. 16 w + 15, lanes over rows
+    if (sym && d > 0) {
+      float* tout = tbuf + b_index(S, qt, d) * (KBQ * KBN);
+      const float nx0 = q0 + lane < n ? norms[q0 + lane] : INFINITY;
+      const float nx1 = q0 + 64 + lane < n ? norms[q0 + 64 + lane] : INFINITY;
+#pragma unroll 4
+      for (int cc = 0; cc < 16; ++cc) {
+        const int c = 16 * w + cc;
+        tout[c * KBQ + lane] = Ss[lane * SLD + c] + nx0;
+        tout[c * KBQ + 64 + lane] = Ss[(64 + lane) * SLD + c] + nx1;
+      }
+    }
     // stage 0 of the next tile is fetched now and lands behind the top-K' work below
-    if (t + 1 < te) stage_load<PREC>(pre, xsrc, mp, n, ((t + 1) / NT) * KBQ, ((t + 1) % NT) * KBN, 0);
-    // top-K' update: wave w owns query rows RPW*w .. RPW*w+RPW-1 of the tile.  A cheap,
-    // unrolled filter marks the rows with any score below their threshold; only those
-    // rows are then swapped into working registers and updated (one copy of the code).
-    uint32_t need = 0;
+    int64_t nqt = qt, nd = d;
+    a_next(S, nqt, nd);
+    if (t + 1 < te) stage_load<PREC>(pre, xsrc, mp, n, nqt * KBQ, a_db(S, nqt, nd) * KBN, 0);
+    const float* srow = Ss + RPW * w * SLD + lane;
+    const float nj0 = j0 + lane < n ? norms[j0 + lane] : 0.0f;
+    const float nj1 = j0 + 64 + lane < n ? norms[j0 + 64 + lane] : 0.0f;
+    const auto score = [&](int rr, int h) { return srow[rr * SLD + 64 * h] + (h ? nj1 : nj0); };
+    lists_apply(lh, ll, lists_filter(lh, score, kc, nocap), score, (uint32_t)j0, kc, lane, nocap);
+    __syncthreads();
+    qt = nqt;
+    d = nd;
+  }
+  flush();
+}
+
+// The row-side lists of the symmetric schedule are complete once the GEMM kernel ends: the
+// K'-th key of their merge (one wave per query; each list ascending, read in reverse) bounds
+// the query's final K'-th key from above.
+__global__ __launch_bounds__(256) void knn_rowcap_kernel(int64_t n, int kc, int64_t GA, int nslot,
+                                                          const float* __restrict__ cand_s,
+                                                          const int* __restrict__ cand_j,
+                                                          uint32_t* __restrict__ rowcap) {
+  const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int64_t q = (int64_t)blockIdx.x * 4 + wv;
+  if (q >= n) return;                       // whole wave exits together
+  const TileSched S = make_sched(n, 1);
+  const int64_t qt = q / KBQ, row = q % KBQ;
+  const int64_t na = segments(a_start(S, qt), a_len(S, qt), GA, a_pairs(S));
+  const int src = WAVE - 1 - lane;
+  uint32_t lh = KEY_PAD_HI, ll = KEY_PAD_LO;
+  for (int64_t sg = 0; sg < na; ++sg) {
+    const int64_t o = ((qt * nslot + sg) * KBQ + row) * kc + src;
+    uint32_t bh = 0xFFFFFFFFu, bl = 0xFFFFFFFFu;
+    if (src < kc) {
+      bh = f2ord(cand_s[o]);
+      bl = (uint32_t)cand_j[o];
+    }
+    wave_merge64(lh, ll, bh, bl);
+  }
+  if (lane == 0) rowcap[q] = rdlane_u(lh, kc - 1);
+}
+
+// Column side of the symmetric schedule: the queries of column tile j scan the transposed
+// tiles of the pairs ((j - d) mod T, j), d = 1 .. b_len(j), with the register lists of the
+// GEMM kernel; their lists go to slots slot0 + (rank among the workgroups sharing j).
+// Streams the tiles once (the next pair's scores load behind the current top-K' work) and
+// does no arithmetic on X.  rowcap[q] (knn_rowcap_kernel) bounds query q's final K'-th key
+// from above; candidates at or above it are skipped.  Everything skipped scores at least
+// the final merged K'-th key, which is what the re-rank's certificate needs.
+__global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) void knn_column_topk_kernel(
+    const float* __restrict__ tbuf, int64_t n, int kc, int64_t G, int slot0, int nslot,
+    const uint32_t* __restrict__ rowcap, float* __restrict__ cand_s, int* __restrict__ cand_j) {
+  const int tid = threadIdx.x;
+  const int w = tid / WAVE, lane = tid % WAVE;
+  const TileSched S = make_sched(n, 1);
+  const int64_t P = b_pairs(S);
+  const int64_t bid = blockIdx.x;
+  const int64_t L = (G % 8 == 0) ? (bid % 8) * (G / 8) + bid / 8 : bid;
+  const int64_t tb = (L * P) / G, te = ((L + 1) * P) / G;
+
+  uint32_t lh[RPW], ll[RPW], cap[RPW];
+  int64_t cur_j = -1;
+  auto flush = [&]() {
+    if (cur_j < 0) return;
+    const int64_t seg = slot0 + L - range_owner(b_start(S, cur_j), G, P);
 #pragma unroll
     for (int rr = 0; rr < RPW; ++rr) {
-      const int row = RPW * w + rr;
-      const uint32_t th = rdlane_u(lh[rr], kc - 1);
-      const bool hit = (f2ord(Ss[row * SLD + lane]) < th) || (f2ord(Ss[row * SLD + 64 + lane]) < th);
-      need |= (__ballot(hit) != 0ull ? 1u : 0u) << rr;
-    }
-    while (need) {
-      const int rr = __ffs(need) - 1;
-      need &= need - 1;
-      uint32_t wh = lh[0], wl = ll[0];
-#pragma unroll
-      for (int r = 1; r < RPW; ++r) {
-        wh = rr == r ? lh[r] : wh;
-        wl = rr == r ? ll[r] : wl;
-      }
-      const int row = RPW * w + rr;
-      row_update(wh, wl, f2ord(Ss[row * SLD + lane]), (uint32_t)(j0 + lane),
-                 f2ord(Ss[row * SLD + 64 + lane]), (uint32_t)(j0 + 64 + lane), kc);
-#pragma unroll
-      for (int r = 0; r < RPW; ++r) {
-        lh[r] = rr == r ? wh : lh[r];
-        ll[r] = rr == r ? wl : ll[r];
+      const int64_t gi = cur_j * KBQ + RPW * w + rr;
+      if (gi < n && lane < kc) {
+        const int64_t o = ((cur_j * nslot + seg) * KBQ + RPW * w + rr) * kc + lane;
+        cand_s[o] = ord2f(lh[rr]);
+        cand_j[o] = (int)ll[rr];
       }
     }
-    __syncthreads();
+  };
+  // wave w's rows of transposed tile t (rows RPW w + rr, candidates lane and 64 + lane) go
+  // global -> registers (loaded one pair ahead) -> the wave's own LDS rows, which the filter
+  // and the list updates read like the GEMM kernel's score tile
+  __shared__ float rows_lds[KNT / WAVE][RPW][KBN];
+  float (*my)[KBN] = rows_lds[w];
+  float c0[RPW], c1[RPW];
+  auto fetch = [&](int64_t t) {
+    const float* trow = tbuf + t * (KBQ * KBN) + RPW * w * KBN + lane;
+#pragma unroll
+    for (int rr = 0; rr < RPW; ++rr) {
+      c0[rr] = trow[rr * KBN];
+      c1[rr] = trow[rr * KBN + 64];
+    }
+  };
+  int64_t j = 0, d = 1;
+  if (tb < te) {
+    b_pair(S, tb, j, d);
+    fetch(tb);
+  }
+  for (int64_t t = tb; t < te; ++t) {
+    if (j != cur_j) {
+      flush();
+      cur_j = j;
+#pragma unroll
+      for (int rr = 0; rr < RPW; ++rr) {
+        lh[rr] = KEY_PAD_HI;
+        ll[rr] = KEY_PAD_LO;
+      }
+      // lane rr < RPW holds row RPW w + rr's bound (rows past n are never flushed)
+      const int64_t gq = j * KBQ + RPW * w + lane;
+      const uint32_t mine = lane < RPW && gq < n ? rowcap[gq] : 0xFFFFFFFFu;
+#pragma unroll
+      for (int rr = 0; rr < RPW; ++rr) cap[rr] = rdlane_u(mine, rr);
+    }
+    // only this wave touches its LDS rows, and its earlier reads are complete (in order)
+#pragma unroll
+    for (int rr = 0; rr < RPW; ++rr) {
+      my[rr][lane] = c0[rr];
+      my[rr][64 + lane] = c1[rr];
+    }
+    const uint32_t need = lists_filter(lh, [&](int rr, int h) { return h ? c1[rr] : c0[rr]; }, kc, cap);
+    if (t + 1 < te) fetch(t + 1);
+    const int64_t i = (j - d + S.T) % S.T;   // the pair's row tile: the candidates
+    lists_apply(lh, ll, need, [&](int rr, int h) { return my[rr][64 * h + lane]; }, (uint32_t)(i * KBQ),
+                kc, lane, cap);
+    if (++d > b_len(S, j)) {
+      ++j;
+      d = 1;
+    }
   }
   flush();
 }
@@ -659,23 +916,25 @@ __global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
 // merge + float32 re-rank + certificate.  One wave per query, 4 queries per block.
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void knn_rerank_kernel(
-    const float* __restrict__ X, int64_t n, int64_t m, int64_t ldx, int k, int kc, int64_t G,
-    int smax, const float* __restrict__ cand_s, const int* __restrict__ cand_j,
+    const float* __restrict__ X, int64_t n, int64_t m, int64_t ldx, int k, int kc, int sym,
+    int64_t GA, int64_t GB, int slotb, int nslot, const float* __restrict__ cand_s,
+    const int* __restrict__ cand_j,
     const float* __restrict__ norms, const float* __restrict__ radius,
     const float* __restrict__ stats, int include_self, int32_t* __restrict__ idx_out,
     float* __restrict__ d2_out, uint8_t* __restrict__ kflags) {
   const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
   const int64_t qi = (int64_t)blockIdx.x * 4 + wv;
   if (qi >= n) return;                      // whole wave exits together
-  const int64_t QT = (n + KBQ - 1) / KBQ;
-  const int64_t NT = (n + KBN - 1) / KBN;
-  const int64_t P = QT * NT;
+  const TileSched S = make_sched(n, sym);
   const int64_t qt = qi / KBQ, row = qi % KBQ;
-  const int64_t nseg = range_owner(qt * NT + NT - 1, G, P) - range_owner(qt * NT, G, P) + 1;
+  // list segments: row side (slots 0 ..), column side (slots slotb ..)
+  const int64_t na = segments(a_start(S, qt), a_len(S, qt), GA, a_pairs(S));
+  const int64_t nb = sym ? segments(b_start(S, qt), b_len(S, qt), GB, b_pairs(S)) : 0;
   // merge the segment lists (each ascending; read in reverse, so descending) into the 64 best
   uint32_t lh = KEY_PAD_HI, ll = KEY_PAD_LO;
-  for (int64_t sg = 0; sg < nseg; ++sg) {
-    const int64_t o = ((qt * smax + sg) * KBQ + row) * kc;
+  for (int64_t sg = 0; sg < na + nb; ++sg) {
+    const int64_t slot = sg < na ? sg : slotb + (sg - na);
+    const int64_t o = ((qt * nslot + slot) * KBQ + row) * kc;
     uint32_t bh = 0xFFFFFFFFu, bl = 0xFFFFFFFFu;
     const int src = WAVE - 1 - lane;
     if (src < kc) {
@@ -780,8 +1039,9 @@ __global__ __launch_bounds__(256) void knn_rerank_kernel(
       const double nmax = (double)stats[0], emax = (double)stats[1], ei = (double)radius[qi];
       const double gm = (double)(m + 8) * u / (1.0 - (double)(m + 8) * u);
       // |gemm d2 - ||xc_i - xc_j||^2|: rounding of the low-precision copy, fp32 dot and norms
+      // (5 u: the norm add, plus the separately rounded fp8 cross term, |2 x_i . x_j| <= ni + nmax^2)
       const double E = 2.0 * (ei * (nmax + emax) + rn * emax) + 2.0 * gm * (rn + ei) * (nmax + emax) +
-                       4.0 * u * (ni + nmax * nmax) + gm * (ni + nmax * nmax);
+                       5.0 * u * (ni + nmax * nmax) + gm * (ni + nmax * nmax);
       const double lo2 = ni + (double)s_last - E;
       // centring rounding: | ||xc_i - xc_j|| - ||x_i - x_j|| | <= u (||xc_i|| + ||xc_j||) (1+u)
       const double lo = (lo2 > 0.0 ? sqrt(lo2) : 0.0) - 1.0001 * u * (rn + nmax);
@@ -801,17 +1061,20 @@ static int64_t knn_mp(int64_t m, int precision) {
   return ((m + bk - 1) / bk) * bk;
 }
 
-// Workgroups of the GEMM stage: about 2 per CU (register and LDS bound), never fewer
-// than the query tiles (so a range spans at most two), a multiple of 8 for the XCD map.
-static int64_t knn_groups(int64_t n) {
-  const int64_t QT = (n + KBQ - 1) / KBQ, NT = (n + KBN - 1) / KBN, P = QT * NT;
+// Workgroups of a list stage over P tile pairs: about 2 per CU (register and LDS bound),
+// never fewer than the row tiles, a multiple of 8 for the XCD map.
+static int64_t knn_groups(int64_t P, int64_t T) {
   int64_t G = 512;
-  if (G < QT) G = QT;
+  if (G < T) G = T;
   if (G > P) G = P;
   if (G >= 8) G = (G + 7) / 8 * 8;
   if (G > P) G = P;
   return G;
 }
+
+// The symmetric schedule keeps one transposed 64 KiB score tile per off-diagonal pair in
+// the workspace; beyond this many bytes (n above about 65536) the full schedule runs.
+constexpr size_t KNN_SYM_MAX_BYTES = (size_t)8 << 30;
 
 KnnPlan knn_plan(int64_t n, int64_t m, int k, int kc, int precision) {
   KnnPlan p{};
@@ -820,17 +1083,24 @@ KnnPlan knn_plan(int64_t n, int64_t m, int k, int kc, int precision) {
   p.k = k;
   p.kc = kc;
   p.precision = precision;
-  const int64_t QT = (n + KBQ - 1) / KBQ;
-  p.groups = knn_groups(n);
-  {
-    // most workgroups sharing one query tile under the range schedule
-    const int64_t NT = (n + KBN - 1) / KBN, P = QT * NT;
-    int64_t smax = 1;
-    for (int64_t qt = 0; qt < QT; ++qt) {
-      const int64_t c = range_owner(qt * NT + NT - 1, p.groups, P) - range_owner(qt * NT, p.groups, P) + 1;
-      if (c > smax) smax = c;
-    }
-    p.smax = (int)smax;
+  const int64_t T = (n + KBQ - 1) / KBQ;
+  const size_t tile_b = (size_t)KBQ * KBN * 4;
+  p.tiles = T;
+  p.sym = (T >= 2 && (size_t)(T * (T - 1) / 2) * tile_b <= KNN_SYM_MAX_BYTES) ? 1 : 0;
+  const TileSched S = make_sched(n, p.sym);
+  p.pairs_a = a_pairs(S);
+  p.groups = knn_groups(p.pairs_a, T);
+  p.smax = 1;
+  for (int64_t i = 0; i < T; ++i) {
+    const int64_t c = segments(a_start(S, i), a_len(S, i), p.groups, p.pairs_a);
+    if (c > p.smax) p.smax = (int)c;
+  }
+  p.pairs_b = p.sym ? b_pairs(S) : 0;
+  p.groups_b = p.pairs_b > 0 ? knn_groups(p.pairs_b, T) : 0;
+  p.smax_b = 0;
+  for (int64_t j = 0; p.pairs_b > 0 && j < T; ++j) {
+    const int64_t c = segments(b_start(S, j), b_len(S, j), p.groups_b, p.pairs_b);
+    if (c > p.smax_b) p.smax_b = (int)c;
   }
   const int64_t mp = knn_mp(m, precision);
   const int64_t parts = KPARTS;
@@ -840,11 +1110,13 @@ KnnPlan knn_plan(int64_t n, int64_t m, int k, int kc, int precision) {
   p.off_norm = off;   off += align256((size_t)n * 4);
   p.off_colsum = off; off += align256((size_t)parts * m * 8 + (size_t)m * 4);
   p.off_stats = off;  off += align256((size_t)n * 4 + 64);
-  const size_t cand = (size_t)QT * p.smax * KBQ * kc * 4;
+  const size_t cand = (size_t)T * (p.smax + p.smax_b) * KBQ * kc * 4;
   p.off_cand_s = off; off += align256(cand);
   p.off_cand_j = off; off += align256(cand);
   p.off_xlow = off;
   p.off_scale = off;  off += precision == 2 ? align256((size_t)n * 4) : 0;
+  p.off_cap = off;    off += p.sym ? align256((size_t)n * 4) : 0;
+  p.off_tbuf = off;   off += (size_t)p.pairs_b * tile_b;
   p.total = off;
   return p;
 }
@@ -896,28 +1168,43 @@ hipError_t launch_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int k, 
     (void)hipGetLastError();
     attr_set = true;
   }
+  float* tbuf = reinterpret_cast<float*>(base + plan.off_tbuf);
+  const int nslot = plan.smax + plan.smax_b;
+  const int self = include_self ? 1 : 0;
   const dim3 grid((unsigned)plan.groups);
   timing_begin(4, stream);
   if (precision == 0) {
     hipLaunchKernelGGL(knn_gemm_topk_kernel<0>, grid, dim3(KNT), gemm_lds_bytes<0>(), stream,
-                       (const void*)xc, mp, norms, scales, n, kc, plan.groups, plan.smax,
-                       include_self ? 1 : 0, cand_s, cand_j);
+                       (const void*)xc, mp, norms, scales, n, kc, plan.sym, plan.groups, nslot, self,
+                       cand_s, cand_j, tbuf);
   } else if (precision == 1) {
     hipLaunchKernelGGL(knn_gemm_topk_kernel<1>, grid, dim3(KNT), gemm_lds_bytes<1>(), stream,
-                       (const void*)xc, mp, norms, scales, n, kc, plan.groups, plan.smax,
-                       include_self ? 1 : 0, cand_s, cand_j);
+                       (const void*)xc, mp, norms, scales, n, kc, plan.sym, plan.groups, nslot, self,
+                       cand_s, cand_j, tbuf);
   } else {
     hipLaunchKernelGGL(knn_gemm_topk_kernel<2>, grid, dim3(KNT), gemm_lds_bytes<2>(), stream,
-                       (const void*)xc, mp, norms, scales, n, kc, plan.groups, plan.smax,
-                       include_self ? 1 : 0, cand_s, cand_j);
+                       (const void*)xc, mp, norms, scales, n, kc, plan.sym, plan.groups, nslot, self,
+                       cand_s, cand_j, tbuf);
   }
   timing_end(4, stream);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (plan.pairs_b > 0) {
+    uint32_t* rowcap = reinterpret_cast<uint32_t*>(base + plan.off_cap);
+    timing_begin(9, stream);
+    hipLaunchKernelGGL(knn_rowcap_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream, n, kc,
+                       plan.groups, nslot, (const float*)cand_s, (const int*)cand_j, rowcap);
+    hipLaunchKernelGGL(knn_column_topk_kernel, dim3((unsigned)plan.groups_b), dim3(KNT), 0, stream,
+                       (const float*)tbuf, n, kc, plan.groups_b, plan.smax, nslot,
+                       (const uint32_t*)rowcap, cand_s, cand_j);
+    timing_end(9, stream);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   timing_begin(5, stream);
   hipLaunchKernelGGL(knn_rerank_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream, X, n, m,
-                     ldx, k, kc, plan.groups, plan.smax, cand_s, cand_j, norms, radius, stats,
-                     include_self ? 1 : 0, idx, d2, kflags);
+                     ldx, k, kc, plan.sym, plan.groups, plan.groups_b, plan.smax, nslot, cand_s, cand_j,
+                     norms, radius, stats, self, idx, d2, kflags);
   timing_end(5, stream);
   return hipGetLastError();
 }

@@ -20,9 +20,16 @@ struct KnnPlan {
   int64_t n, m;
   int k, kc;          // neighbours, candidates kept per query (rerank_factor * k)
   int precision;
-  int64_t groups;     // workgroups of the GEMM/top-k stage
-  int smax;           // list segments reserved per query tile
-  size_t off_xc, off_norm, off_colsum, off_stats, off_cand_s, off_cand_j, off_xlow, off_scale, total;
+  int64_t tiles;      // 128-point tiles
+  int sym;            // 1: symmetric tile-pair schedule (row side + column side), 0: full
+  int64_t pairs_a;    // tile pairs of the GEMM/top-k (row side) stage
+  int64_t groups;     // its workgroups
+  int smax;           // its list segments reserved per row tile
+  int64_t pairs_b;    // transposed tiles of the column-side stage (0 unless sym)
+  int64_t groups_b;   // its workgroups
+  int smax_b;         // its list segments reserved per column tile
+  size_t off_xc, off_norm, off_colsum, off_stats, off_cand_s, off_cand_j, off_xlow, off_scale;
+  size_t off_cap, off_tbuf, total;
 };
 
 KnnPlan knn_plan(int64_t n, int64_t m, int k, int kc, int precision);

@@ -118,3 +118,42 @@ def test_knn_low_precision_full_size(name, precision):
     bad_big, bad_small, nbig, _ = knn_set_report(idx, X, rows, k)
     print(f"  mismatches: {bad_big} (gap above bound, of {nbig}), {bad_small} (below)", flush=True)
     assert bad_big == 0
+
+
+@pytest.mark.parametrize("n", [1, 2, 100, 128, 129, 200, 256, 300, 385, 512, 650])
+def test_knn_tile_counts(n):
+    """One to six 128-point tiles with ragged tails: the symmetric tile-pair schedule's
+    small cases (one tile; two tiles, whose second gets only the transposed pair; an even
+    tile count, where half the row tiles own the pair at distance T/2)."""
+    import paper_2606_06329_amd as P
+    from paper_2606_06329_amd._lib import MecucoError
+    X = np.ascontiguousarray(synth.swissroll(n=max(n, 3), m=19, seed=1000 + n)[:n])
+    if n <= 2:                       # k >= 2 neighbours need n >= 3 points
+        with pytest.raises(MecucoError):
+            P.knn(to_dev(X), 2)
+        return
+    k = min(6, n - 1)
+    print(f"knn tiles n={n} k={k}", flush=True)
+    idx, d2, fl = P.knn(to_dev(X), k)
+    idx = idx.cpu().numpy()
+    bad_big, bad_small, nbig, _ = knn_set_report(idx, X, np.arange(n), k)
+    print(f"  mismatches: {bad_big} (gap above bound, of {nbig}), {bad_small} (below)", flush=True)
+    assert bad_big == 0
+    assert np.all((idx >= 0) & (idx < n))
+    assert not np.any(idx == np.arange(n)[:, None])
+
+
+def test_knn_full_schedule_large_n():
+    """n = 70000 (548 tiles): past the symmetric schedule's workspace limit, so every tile
+    pair is scored in both orders; sets exact on sampled rows."""
+    import paper_2606_06329_amd as P
+    X = synth.swissroll(n=70000, m=24, seed=4077)
+    k = 10
+    print("knn full schedule n=70000 m=24 k=10", flush=True)
+    idx, _, fl = P.knn(to_dev(X), k)
+    idx = idx.cpu().numpy()
+    rows = np.random.default_rng(6).choice(70000, 200, replace=False)
+    rows = np.concatenate([rows, [0, 69999, 69888]])   # first and last tiles
+    bad_big, bad_small, nbig, _ = knn_set_report(idx, X, rows, k)
+    print(f"  mismatches: {bad_big} (gap above bound, of {nbig}), {bad_small} (below)", flush=True)
+    assert bad_big == 0

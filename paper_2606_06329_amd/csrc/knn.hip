@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void knn_mean_kernel(const double* __restrict_
 __global__ __launch_bounds__(256) void knn_center_kernel(
     const float* __restrict__ X, int64_t n, int64_t m, int64_t ldx, int64_t mp,
     const float* __restrict__ mu, void* __restrict__ xout, float* __restrict__ scales,
-    float* __restrict__ norms, float* __restrict__ radius, int precision) {
+    float* __restrict__ norms, float* __restrict__ radius, int precision, uint32_t* __restrict__ thr) {
   const int64_t r = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
   const int lane = threadIdx.x % WAVE;
   if (r >= n) return;
@@ -115,6 +115,7 @@ __global__ __launch_bounds__(256) void knn_center_kernel(
     norms[r] = (float)s;
     radius[r] = (float)(sqrt(e) * (1.0 + 0x1p-20));   // rounded up: it bounds an error
     if (scales) scales[r] = sc;
+    thr[r] = 0xFFFFFFFFu;   // no K'-th key published yet
   }
 }
 
@@ -666,18 +667,19 @@ __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64
 
 // Top-K' update of the RPW rows a wave owns against 128 new candidates c0 .. c0 + 127, in
 // two steps.  lists_filter: a cheap, unrolled pass marks the rows with any score below
-// their threshold (the list's K'-th key and cap[rr], the caller's upper bound for row rr);
+// their threshold (the list's K'-th key and lane rr of capv, the caller's upper bound for
+// row rr);
 // score(rr, h) is row rr's score of candidate c0 + 64 h + lane, rr a compile-time index.
 // lists_apply: only the marked rows are swapped into working registers and updated (one
 // copy of the code); score(rr, h) is read again with rr a run-time index.
 template <class F>
 __device__ __forceinline__ uint32_t lists_filter(const uint32_t (&lh)[RPW], const F& score, int kc,
-                                                 const uint32_t (&cap)[RPW]) {
+                                                 uint32_t capv) {
   uint32_t need = 0;
 #pragma unroll
   for (int rr = 0; rr < RPW; ++rr) {
     const uint32_t own = rdlane_u(lh[rr], kc - 1);
-    const uint32_t th = own < cap[rr] ? own : cap[rr];
+    const uint32_t th = umin32(own, rdlane_u(capv, rr));
     // no short-circuit: every score load is issued up front
     const bool hit = (f2ord(score(rr, 0)) < th) | (f2ord(score(rr, 1)) < th);
     need |= (__ballot(hit) != 0ull ? 1u : 0u) << rr;
@@ -688,17 +690,17 @@ __device__ __forceinline__ uint32_t lists_filter(const uint32_t (&lh)[RPW], cons
 template <class F>
 __device__ __forceinline__ void lists_apply(uint32_t (&lh)[RPW], uint32_t (&ll)[RPW], uint32_t need,
                                             const F& score, uint32_t c0, int kc, int lane,
-                                            const uint32_t (&cap)[RPW]) {
+                                            uint32_t capv) {
   while (need) {
     const int rr = __ffs(need) - 1;
     need &= need - 1;
-    uint32_t wh = lh[0], wl = ll[0], cp = cap[0];
+    uint32_t wh = lh[0], wl = ll[0];
 #pragma unroll
     for (int r = 1; r < RPW; ++r) {
       wh = rr == r ? lh[r] : wh;
       wl = rr == r ? ll[r] : wl;
-      cp = rr == r ? cap[r] : cp;
     }
+    const uint32_t cp = rdlane_u(capv, rr);
     row_update(wh, wl, f2ord(score(rr, 0)), c0 + (uint32_t)lane, f2ord(score(rr, 1)),
                c0 + 64u + (uint32_t)lane, kc, cp);
 #pragma unroll
@@ -713,13 +715,18 @@ __device__ __forceinline__ void lists_apply(uint32_t (&lh)[RPW], uint32_t (&ll)[
 // equal ranges of pairs.  Each workgroup keeps the lists of the current row tile's 128
 // queries in registers (wave w: rows RPW w .. RPW w + RPW - 1) and writes them to list
 // slot (its rank among the workgroups sharing that row tile) when the row tile changes.
+// The workgroups sharing a row tile run at the same time: each publishes an updated row's
+// K'-th key to thr[q] (atomic minimum) and filters against the smallest one published.
+// Any list's K'-th key bounds the final one from above, so a candidate skipped this way
+// scores at least the final merged K'-th key, which is all the re-rank's certificate needs.
 // Under the symmetric schedule every off-diagonal pair also leaves its transposed tile in
 // tbuf for the column pass.
 template <int PREC>
 __global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) void knn_gemm_topk_kernel(
     const void* __restrict__ xsrc, int64_t mp, const float* __restrict__ norms,
     const float* __restrict__ scales, int64_t n, int kc, int sym, int64_t G, int nslot,
-    int include_self, float* __restrict__ cand_s, int* __restrict__ cand_j, float* __restrict__ tbuf) {
+    int include_self, float* __restrict__ cand_s, int* __restrict__ cand_j, float* __restrict__ tbuf,
+    uint32_t* __restrict__ thr) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
   const int w = tid / WAVE, lane = tid % WAVE;
@@ -732,9 +739,6 @@ __global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
   const float* Ss = reinterpret_cast<const float*>(smem);
 
   uint32_t lh[RPW], ll[RPW];   // per-row sorted key lists (score order bits, index)
-  uint32_t nocap[RPW];
-#pragma unroll
-  for (int rr = 0; rr < RPW; ++rr) nocap[rr] = 0xFFFFFFFFu;
   int64_t cur_qt = -1;
   auto flush = [&]() {
     if (cur_qt < 0) return;
@@ -767,6 +771,9 @@ __global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     }
     const int64_t j0 = a_db(S, qt, d) * KBN;
     const int64_t q0 = qt * KBQ;
+    // lane rr < RPW: the smallest K'-th key any workgroup has published for row RPW w + rr
+    const int64_t gq = q0 + RPW * w + lane;
+    const uint32_t capv = lane < RPW && gq < n ? thr[gq] : 0xFFFFFFFFu;
     tile_scores<PREC>(xsrc, mp, norms, scales, n, q0, j0, include_self, smem, pre);
     __syncthreads();
     // the symmetric schedule's off-diagonal pairs leave the transposed scores for the column
@@ -791,7 +798,18 @@ __global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     const float nj0 = j0 + lane < n ? norms[j0 + lane] : 0.0f;
     const float nj1 = j0 + 64 + lane < n ? norms[j0 + 64 + lane] : 0.0f;
     const auto score = [&](int rr, int h) { return srow[rr * SLD + 64 * h] + (h ? nj1 : nj0); };
-    lists_apply(lh, ll, lists_filter(lh, score, kc, nocap), score, (uint32_t)j0, kc, lane, nocap);
+    const uint32_t need = lists_filter(lh, score, kc, capv);
+    lists_apply(lh, ll, need, score, (uint32_t)j0, kc, lane, capv);
+    if (need) {
+      // publish the updated rows' K'-th keys (lane rr: row RPW w + rr)
+      uint32_t mine = 0xFFFFFFFFu;
+#pragma unroll
+      for (int rr = 0; rr < RPW; ++rr) {
+        const uint32_t kth = rdlane_u(lh[rr], kc - 1);
+        mine = lane == rr ? kth : mine;
+      }
+      if (lane < RPW && ((need >> lane) & 1u) && gq < n && mine < capv) atomicMin(thr + gq, mine);
+    }
     __syncthreads();
     qt = nqt;
     d = nd;
@@ -844,7 +862,8 @@ __global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
   const int64_t L = (G % 8 == 0) ? (bid % 8) * (G / 8) + bid / 8 : bid;
   const int64_t tb = (L * P) / G, te = ((L + 1) * P) / G;
 
-  uint32_t lh[RPW], ll[RPW], cap[RPW];
+  uint32_t lh[RPW], ll[RPW];
+  uint32_t capv = 0xFFFFFFFFu;   // lane rr: the bound of row RPW w + rr
   int64_t cur_j = -1;
   auto flush = [&]() {
     if (cur_j < 0) return;
@@ -889,9 +908,7 @@ __global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
       }
       // lane rr < RPW holds row RPW w + rr's bound (rows past n are never flushed)
       const int64_t gq = j * KBQ + RPW * w + lane;
-      const uint32_t mine = lane < RPW && gq < n ? rowcap[gq] : 0xFFFFFFFFu;
-#pragma unroll
-      for (int rr = 0; rr < RPW; ++rr) cap[rr] = rdlane_u(mine, rr);
+      capv = lane < RPW && gq < n ? rowcap[gq] : 0xFFFFFFFFu;
     }
     // only this wave touches its LDS rows, and its earlier reads are complete (in order)
 #pragma unroll
@@ -899,11 +916,11 @@ __global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
       my[rr][lane] = c0[rr];
       my[rr][64 + lane] = c1[rr];
     }
-    const uint32_t need = lists_filter(lh, [&](int rr, int h) { return h ? c1[rr] : c0[rr]; }, kc, cap);
+    const uint32_t need = lists_filter(lh, [&](int rr, int h) { return h ? c1[rr] : c0[rr]; }, kc, capv);
     if (t + 1 < te) fetch(t + 1);
     const int64_t i = (j - d + S.T) % S.T;   // the pair's row tile: the candidates
     lists_apply(lh, ll, need, [&](int rr, int h) { return my[rr][64 * h + lane]; }, (uint32_t)(i * KBQ),
-                kc, lane, cap);
+                kc, lane, capv);
     if (++d > b_len(S, j)) {
       ++j;
       d = 1;
@@ -1116,6 +1133,7 @@ KnnPlan knn_plan(int64_t n, int64_t m, int k, int kc, int precision) {
   p.off_xlow = off;
   p.off_scale = off;  off += precision == 2 ? align256((size_t)n * 4) : 0;
   p.off_cap = off;    off += p.sym ? align256((size_t)n * 4) : 0;
+  p.off_thr = off;    off += align256((size_t)n * 4);
   p.off_tbuf = off;   off += (size_t)p.pairs_b * tile_b;
   p.total = off;
   return p;
@@ -1148,8 +1166,9 @@ hipError_t launch_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int k, 
                      (int)parts, n, mu);
   timing_end(1, stream);
   timing_begin(2, stream);
+  uint32_t* thr = reinterpret_cast<uint32_t*>(base + plan.off_thr);
   hipLaunchKernelGGL(knn_center_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream, X, n,
-                     m, ldx, mp, mu, xc, scales, norms, radius, precision);
+                     m, ldx, mp, mu, xc, scales, norms, radius, precision, thr);
   timing_end(2, stream);
   timing_begin(3, stream);
   hipLaunchKernelGGL(knn_stats_kernel, dim3(1), dim3(256), 0, stream, norms, radius, n, stats);
@@ -1176,15 +1195,15 @@ hipError_t launch_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int k, 
   if (precision == 0) {
     hipLaunchKernelGGL(knn_gemm_topk_kernel<0>, grid, dim3(KNT), gemm_lds_bytes<0>(), stream,
                        (const void*)xc, mp, norms, scales, n, kc, plan.sym, plan.groups, nslot, self,
-                       cand_s, cand_j, tbuf);
+                       cand_s, cand_j, tbuf, thr);
   } else if (precision == 1) {
     hipLaunchKernelGGL(knn_gemm_topk_kernel<1>, grid, dim3(KNT), gemm_lds_bytes<1>(), stream,
                        (const void*)xc, mp, norms, scales, n, kc, plan.sym, plan.groups, nslot, self,
-                       cand_s, cand_j, tbuf);
+                       cand_s, cand_j, tbuf, thr);
   } else {
     hipLaunchKernelGGL(knn_gemm_topk_kernel<2>, grid, dim3(KNT), gemm_lds_bytes<2>(), stream,
                        (const void*)xc, mp, norms, scales, n, kc, plan.sym, plan.groups, nslot, self,
-                       cand_s, cand_j, tbuf);
+                       cand_s, cand_j, tbuf, thr);
   }
   timing_end(4, stream);
   e = hipGetLastError();

@@ -98,9 +98,10 @@ extern "C" {
  * difference-form distances sum_a (x_a - y_a)^2 on the original X and the k
  * smallest are kept, ordered by (distance, index).  With rerank_factor == 1 the
  * GEMM distances decide (MC_FP32 only).  The distance matrix is symmetric: while
- * the workspace for it stays within 8 GiB (n up to 65536), each unordered pair
+ * the workspace for it stays within 32 GiB (n up to 131072), each unordered pair
  * of 128-point tiles is scored once and its transposed 64 KiB score tile serves
- * the other tile's queries, so the workspace then holds about n^2 / 2 floats.
+ * the other tile's queries, so the workspace then holds about n^2 / 2 floats
+ * (0.8 GB at n = 20000, 20 GB at n = 100000).
  *
  *   X            [n x ldx] float32, device
  *   n, m, ldx    points, dimensions, row stride (elements)

@@ -58,11 +58,11 @@ def default_rerank(k: int, n: int, precision: str = "fp32") -> int:
 
 # the library's workspace limit for the symmetric tile-pair schedule (one 64 KiB transposed
 # score tile per unordered pair of 128-point tiles)
-KNN_SYM_MAX_BYTES = 8 << 30
+KNN_SYM_MAX_BYTES = 32 << 30
 
 
 def knn_symmetric(n: int) -> bool:
-    """Whether mc_knn scores each unordered pair of 128-point tiles once (n up to about 65536)
+    """Whether mc_knn scores each unordered pair of 128-point tiles once (n up to 131072)
     rather than every ordered pair: its distance GEMM then does n (n + 1) m flop, not 2 n^2 m."""
     T = -(-int(n) // 128)
     return T >= 2 and (T * (T - 1) // 2) * 65536 <= KNN_SYM_MAX_BYTES

@@ -1090,8 +1090,9 @@ static int64_t knn_groups(int64_t P, int64_t T) {
 }
 
 // The symmetric schedule keeps one transposed 64 KiB score tile per off-diagonal pair in
-// the workspace; beyond this many bytes (n above about 65536) the full schedule runs.
-constexpr size_t KNN_SYM_MAX_BYTES = (size_t)8 << 30;
+// the workspace (20 GB at n = 100000, against 288 GB of HBM); beyond this many bytes (n above
+// 131072) the full schedule runs.
+constexpr size_t KNN_SYM_MAX_BYTES = (size_t)32 << 30;
 
 KnnPlan knn_plan(int64_t n, int64_t m, int k, int kc, int precision) {
   KnnPlan p{};

@@ -144,16 +144,18 @@ def test_knn_tile_counts(n):
 
 
 def test_knn_full_schedule_large_n():
-    """n = 70000 (548 tiles): past the symmetric schedule's workspace limit, so every tile
+    """n = 140000 (1094 tiles): past the symmetric schedule's workspace limit, so every tile
     pair is scored in both orders; sets exact on sampled rows."""
     import paper_2606_06329_amd as P
-    X = synth.swissroll(n=70000, m=24, seed=4077)
+    n = 140000
+    assert not P.knn_symmetric(n)
+    X = synth.swissroll(n=n, m=12, seed=4077)
     k = 10
-    print("knn full schedule n=70000 m=24 k=10", flush=True)
+    print(f"knn full schedule n={n} m=12 k=10", flush=True)
     idx, _, fl = P.knn(to_dev(X), k)
     idx = idx.cpu().numpy()
-    rows = np.random.default_rng(6).choice(70000, 200, replace=False)
-    rows = np.concatenate([rows, [0, 69999, 69888]])   # first and last tiles
+    rows = np.random.default_rng(6).choice(n, 200, replace=False)
+    rows = np.concatenate([rows, [0, n - 1, n - 100]])   # first and last tiles
     bad_big, bad_small, nbig, _ = knn_set_report(idx, X, rows, k)
     print(f"  mismatches: {bad_big} (gap above bound, of {nbig}), {bad_small} (below)", flush=True)
     assert bad_big == 0

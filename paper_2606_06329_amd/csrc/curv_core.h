@@ -207,33 +207,29 @@ __device__ __forceinline__ PointLds point_lds(unsigned char* smem) {
   return P;
 }
 
-// k x k eigen-solve: cyclic Jacobi in parallel (round-robin) order, float64.  On entry
-// JA holds K (k x k, zero-padded to KK) and JV the identity.  The matrix is padded to
-// KK = KMAX (even) with zero rows and columns, which never rotate, so every loop bound is
-// a compile-time constant.  Each round rotates KK/2 disjoint planes; the update works on
-// 2 x 2 blocks of A (pair i x pair i') and on row x of V restricted to one pair, so every
-// thread reads and writes the same cells and the update runs in place.  A round whose
-// planes are all below threshold skips its update.  On return: eigen order in P.ord,
-// sig0 = sigma_1, pe = numerical rank (eigenvalues above max(k, m) * unit * sigma_1 among
-// the first min(k-1, m)), sweep = sweeps used, and P.UT = U_p diag(sigma_p^(-1/2)).
-template <int KMAX, class C>
-__device__ void jacobi_eigen(const PointLds& P, int k, int64_t m, int tg, double unit, double& sig0,
-                             int& pe, int& sweep) {
-  double* JA = P.JA;
-  double* JV = P.JV;
+__device__ __forceinline__ float rsqrt_nr(float x) {
+  float y = __builtin_amdgcn_rsqf(x);
+  return y * fmaf(-0.5f * x * y, y, 1.5f);
+}
+
+// Cyclic Jacobi sweeps in parallel (round-robin) order on the KK x KK matrix A (row stride
+// C::JLD, working type JT), accumulating the rotations into V.  The matrix is padded to
+// KK = KMAX (even) with zero rows and columns, which never rotate, so every loop bound is a
+// compile-time constant.  Each round rotates KK/2 disjoint planes; the update works on 2 x 2
+// blocks of A (pair i x pair i') and on row x of V restricted to one pair, so every thread
+// reads and writes the same cells and the update runs in place.  A round whose planes are
+// all below threshold (|a_pq| <= eps sqrt(|a_pp a_qq|), or the absolute floor) skips its
+// update.  Returns the sweeps used (JAC_MAX_SWEEPS when the limit was hit).
+template <class C, class JT>
+__device__ int jacobi_sweeps(const PointLds& P, JT* JA, JT* JV, int k, int tg, JT eps) {
   int* misc = P.misc;
   constexpr int KK = C::KK;
   constexpr int HP = KK / 2;
-  double trace = 0.0;
-  for (int e = tg; e < (KK - 1) * HP; e += C::NTG) {
-    const int r = e / HP, i = e % HP;
-    const int pa = rr_player(i, r, KK), pb = rr_player(KK - 1 - i, r, KK);
-    P.pairs[e] = (uint16_t)((pa < pb ? pa : pb) | ((pa < pb ? pb : pa) << 8));
-  }
-  gsync<C::NW>();
+  JT* ROT = reinterpret_cast<JT*>(P.ROT);
+  JT trace = 0;
   for (int x = 0; x < k; ++x) trace += JA[x * C::JLD + x];
-  const double floor_abs = trace * 0x1p-100;
-  sweep = 0;
+  const JT floor_abs = trace * (JT)0x1p-100;
+  int sweep = 0;
   for (; sweep < JAC_MAX_SWEEPS; ++sweep) {
     int swept = 0;
     for (int r = 0; r < KK - 1; ++r) {
@@ -242,20 +238,20 @@ __device__ void jacobi_eigen(const PointLds& P, int k, int64_t m, int tg, double
       if (tg < HP) {
         const int pq = pr[tg];
         const int p = pq & 0xff, q = pq >> 8;
-        const double app = JA[p * C::JLD + p], aqq = JA[q * C::JLD + q], apq = JA[p * C::JLD + q];
-        double c = 1.0, sn = 0.0;
-        const double thr = fmax(0x1p-52 * sqrt(fabs(app) * fabs(aqq)), floor_abs);
+        const JT app = JA[p * C::JLD + p], aqq = JA[q * C::JLD + q], apq = JA[p * C::JLD + q];
+        JT c = 1, sn = 0;
+        const JT thr = fmax(eps * sqrt(fabs(app) * fabs(aqq)), floor_abs);
         if (fabs(apq) > thr) {
           // t = tan(phi), the smaller root of t^2 + 2 t (aqq - app)/(2 apq) - 1 = 0
-          const double d = aqq - app, e2 = 2.0 * apq;
-          const double t0 = e2 / (fabs(d) + sqrt(fma(d, d, e2 * e2)));
-          const double t = d < 0.0 ? -t0 : t0;
-          c = rsqrt_nr(fma(t, t, 1.0));
+          const JT d = aqq - app, e2 = 2 * apq;
+          const JT t0 = e2 / (fabs(d) + sqrt(fma(d, d, e2 * e2)));
+          const JT t = d < 0 ? -t0 : t0;
+          c = rsqrt_nr(fma(t, t, (JT)1));
           sn = t * c;
           rot = 1;
         }
-        P.ROT[tg] = c;
-        P.ROT[C::KK / 2 + tg] = sn;
+        ROT[tg] = c;
+        ROT[C::KK / 2 + tg] = sn;
       }
       rot = __any(rot);                   // the rotating lanes all sit in wave 0
       if constexpr (C::NW > 1) {
@@ -270,19 +266,19 @@ __device__ void jacobi_eigen(const PointLds& P, int k, int64_t m, int tg, double
         const int bi = u / HP, bj = u % HP;
         const int pq1 = pr[bi], pq2 = pr[bj];
         const int p = pq1 & 0xff, q = pq1 >> 8, p2 = pq2 & 0xff, q2 = pq2 >> 8;
-        const double c = P.ROT[bi], sn = P.ROT[C::KK / 2 + bi];
-        const double c2 = P.ROT[bj], s2 = P.ROT[C::KK / 2 + bj];
-        const double a00 = JA[p * C::JLD + p2], a01 = JA[p * C::JLD + q2];
-        const double a10 = JA[q * C::JLD + p2], a11 = JA[q * C::JLD + q2];
+        const JT c = ROT[bi], sn = ROT[C::KK / 2 + bi];
+        const JT c2 = ROT[bj], s2 = ROT[C::KK / 2 + bj];
+        const JT a00 = JA[p * C::JLD + p2], a01 = JA[p * C::JLD + q2];
+        const JT a10 = JA[q * C::JLD + p2], a11 = JA[q * C::JLD + q2];
         // columns: (p2, q2) <- (c2 a_p2 - s2 a_q2, s2 a_p2 + c2 a_q2)
-        const double m00 = c2 * a00 - s2 * a01, m01 = s2 * a00 + c2 * a01;
-        const double m10 = c2 * a10 - s2 * a11, m11 = s2 * a10 + c2 * a11;
+        const JT m00 = c2 * a00 - s2 * a01, m01 = s2 * a00 + c2 * a01;
+        const JT m10 = c2 * a10 - s2 * a11, m11 = s2 * a10 + c2 * a11;
         // rows: (p, q) <- (c m_p - s m_q, s m_p + c m_q)
-        double n00 = c * m00 - sn * m10, n01 = c * m01 - sn * m11;
-        double n10 = sn * m00 + c * m10, n11 = sn * m01 + c * m11;
-        if (bi == bj && sn != 0.0) {
-          n01 = 0.0;
-          n10 = 0.0;
+        JT n00 = c * m00 - sn * m10, n01 = c * m01 - sn * m11;
+        JT n10 = sn * m00 + c * m10, n11 = sn * m01 + c * m11;
+        if (bi == bj && sn != 0) {
+          n01 = 0;
+          n10 = 0;
         }
         JA[p * C::JLD + p2] = n00;
         JA[p * C::JLD + q2] = n01;
@@ -295,8 +291,8 @@ __device__ void jacobi_eigen(const PointLds& P, int k, int64_t m, int tg, double
         if (x < k) {
           const int pq2 = pr[bj];
           const int p2 = pq2 & 0xff, q2 = pq2 >> 8;
-          const double c2 = P.ROT[bj], s2 = P.ROT[C::KK / 2 + bj];
-          const double v0 = JV[x * C::JLD + p2], v1 = JV[x * C::JLD + q2];
+          const JT c2 = ROT[bj], s2 = ROT[C::KK / 2 + bj];
+          const JT v0 = JV[x * C::JLD + p2], v1 = JV[x * C::JLD + q2];
           JV[x * C::JLD + p2] = c2 * v0 - s2 * v1;
           JV[x * C::JLD + q2] = s2 * v0 + c2 * v1;
         }
@@ -304,6 +300,91 @@ __device__ void jacobi_eigen(const PointLds& P, int k, int64_t m, int tg, double
       gsync<C::NW>();
     }
     if (!swept) break;
+  }
+  return sweep;
+}
+
+// k x k eigen-solve of the Gram matrix K.  On entry JA holds K (float64, k x k, zero-padded
+// to KK) and JV the identity.
+//  * F32 = false: float64 Jacobi sweeps to a relative 2^-52.
+//  * F32 = true (bf16 moments): float32 sweeps to 2^-23 on a float32 copy held in the JV
+//    storage.  Their eigenvalue error, about 2^-23 sigma_1, is far below that of the bf16
+//    moments themselves.  A kept spectrum with a near-degenerate pair (|sigma_x - sigma_y| <
+//    2^-13 sigma_1) is re-solved in float64 from the untouched JA; misc[5] records that.
+// On return: eigen order in P.ord, sig0 = sigma_1, pe = numerical rank (eigenvalues above
+// max(k, m) * unit * sigma_1 among the first min(k-1, m)), sweep = sweeps used, and
+// P.UT = U_p diag(sigma_p^(-1/2)).
+template <int KMAX, class C, bool F32 = false>
+__device__ void jacobi_eigen(const PointLds& P, int k, int64_t m, int tg, double unit, double& sig0,
+                             int& pe, int& sweep) {
+  double* JA = P.JA;
+  double* JV = P.JV;
+  int* misc = P.misc;
+  constexpr int KK = C::KK;
+  constexpr int HP = KK / 2;
+  for (int e = tg; e < (KK - 1) * HP; e += C::NTG) {
+    const int r = e / HP, i = e % HP;
+    const int pa = rr_player(i, r, KK), pb = rr_player(KK - 1 - i, r, KK);
+    P.pairs[e] = (uint16_t)((pa < pb ? pa : pb) | ((pa < pb ? pb : pa) << 8));
+  }
+  if constexpr (F32) {
+    float* A32 = reinterpret_cast<float*>(JV);   // the two float32 matrices fill JV's storage
+    float* V32 = A32 + KK * C::JLD;
+    for (int e = tg; e < KK * KK; e += C::NTG) {
+      const int x = e / KK, y = e % KK;
+      A32[x * C::JLD + y] = (float)JA[x * C::JLD + y];
+      V32[x * C::JLD + y] = x == y ? 1.0f : 0.0f;
+    }
+    gsync<C::NW>();
+    sweep = jacobi_sweeps<C, float>(P, A32, V32, k, tg, 0x1p-23f);
+    // near-degenerate pair among the kept eigenvalues (wave 0 holds the KK diagonal lanes)
+    if (tg < WAVE) {
+      bool near = false;
+      if (tg < k) {
+        float s1 = 0.0f;
+        for (int y = 0; y < k; ++y) s1 = fmaxf(s1, A32[y * C::JLD + y]);
+        const float keep = (float)((double)(m > k ? m : k) * unit) * s1;
+        const float lx = A32[tg * C::JLD + tg];
+        if (lx > keep) {
+          for (int y = 0; y < k; ++y) {
+            const float ly = A32[y * C::JLD + y];
+            near |= y != tg && ly > keep && fabsf(lx - ly) < 0x1p-13f * s1;
+          }
+        }
+      }
+      const int anyv = __any(near);
+      if (tg == 0) misc[5] = anyv;
+    }
+    gsync<C::NW>();
+    if (misc[5]) {
+      for (int e = tg; e < KK * KK; e += C::NTG) {
+        const int x = e / KK, y = e % KK;
+        JV[x * C::JLD + y] = (x == y) ? 1.0 : 0.0;
+      }
+      gsync<C::NW>();
+      sweep = jacobi_sweeps<C, double>(P, JA, JV, k, tg, 0x1p-52);
+    } else {
+      // float32 results into the float64 arrays (JA's diagonal, JV), read all before writing
+      constexpr int NPT = (KK * KK + C::NTG - 1) / C::NTG;
+      float vv[NPT];
+#pragma unroll
+      for (int t = 0; t < NPT; ++t) {
+        const int e = tg + t * C::NTG;
+        vv[t] = e < KK * KK ? V32[(e / KK) * C::JLD + e % KK] : 0.0f;
+      }
+      const float dg = tg < KK ? A32[tg * C::JLD + tg] : 0.0f;
+      gsync<C::NW>();
+#pragma unroll
+      for (int t = 0; t < NPT; ++t) {
+        const int e = tg + t * C::NTG;
+        if (e < KK * KK) JV[(e / KK) * C::JLD + e % KK] = (double)vv[t];
+      }
+      if (tg < KK) JA[tg * C::JLD + tg] = (double)dg;
+      gsync<C::NW>();
+    }
+  } else {
+    gsync<C::NW>();
+    sweep = jacobi_sweeps<C, double>(P, JA, JV, k, tg, 0x1p-52);
   }
 
   // ---- eigen order, numerical rank, Ut = U_p / sqrt(sigma) -------------------------------
@@ -579,7 +660,7 @@ __device__ uint8_t patch_front(const PointLds& P, const float* __restrict__ X, i
   tauk = P.RED[15 * C::NW];
   if (misc[1]) return PF_NONFINITE;
 
-  // ---- k x k eigen-solve (float64 Jacobi) on K ---------------------------------------
+  // ---- k x k eigen-solve (Jacobi; float32 sweeps for bf16 moments) on K --------------
   {
     constexpr int KK = C::KK;
     const MomT<PREC>* Krow = mom + (k + 1) * C::NPAD;
@@ -589,7 +670,7 @@ __device__ uint8_t patch_front(const PointLds& P, const float* __restrict__ X, i
       JV[x * C::JLD + y] = (x == y) ? 1.0 : 0.0;
     }
   }
-  jacobi_eigen<KMAX, C>(P, k, m, tg, PREC == MOM_FP64 ? 0x1p-44 : 0x1p-24, sig0, pe, sweep);
+  jacobi_eigen<KMAX, C, PREC == MOM_BF16>(P, k, m, tg, PREC == MOM_FP64 ? 0x1p-44 : 0x1p-24, sig0, pe, sweep);
   gsync<C::NW>();
   return 0;
 }

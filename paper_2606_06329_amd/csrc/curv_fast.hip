@@ -223,6 +223,7 @@ __global__ __launch_bounds__((Fast1CfgSel<KMAX, PREC>::C::NT)) void curv_fast1_k
     const int plim = (int)((int64_t)(k - 1) < m ? (int64_t)(k - 1) : m);
     if (pe < plim) fl |= PF_RANK_DEFICIENT;
     if (sweep >= JAC_MAX_SWEEPS) fl |= PF_JACOBI_MAXSWEEPS;
+    if (P.misc[5]) fl |= PF_EIGEN_FP64;
     kappa_out[i] = (float)kap;
     if (flags_out) flags_out[i] = fl;
   }
@@ -456,11 +457,12 @@ __global__ __launch_bounds__((Fast2CfgSel<KMAX, PREC>::C::NT)) void curv_fast2_k
   // ---- eigen-solve: Ut = U_p diag(sigma_p^(-1/2)) ------------------------------------
   double sig0;
   int pe, sweep;
-  jacobi_eigen<KMAX, C>(P, k, m, tg, PREC == MOM_FP64 ? 0x1p-44 : 0x1p-24, sig0, pe, sweep);
+  jacobi_eigen<KMAX, C, PREC == MOM_BF16>(P, k, m, tg, PREC == MOM_FP64 ? 0x1p-44 : 0x1p-24, sig0, pe, sweep);
   const int plim = (int)((int64_t)(k - 1) < m ? (int64_t)(k - 1) : m);
   uint8_t fl = 0;
   if (pe < plim) fl |= PF_RANK_DEFICIENT;
   if (sweep >= JAC_MAX_SWEEPS) fl |= PF_JACOBI_MAXSWEEPS;
+  if (misc[5]) fl |= PF_EIGEN_FP64;
   if (!(sig0 > 0.0) || tauk == 0.0 || pe == 0) {   // locally flat: kappa = 0
     if (tg == 0) {
       kappa_out[i] = 0.0f;

@@ -137,7 +137,7 @@ int mc_curvature_fast(const float* X, int64_t n, int64_t m, int64_t ldx, const i
   if (mc::launch_curv_fast(X, n, m, ldx, idx, k, precision, variant, kappa_out, flags_out, s) !=
       hipSuccess)
     return MC_ELAUNCH;
-  if (flags & MC_STRICT) return strict_check(flags_out, n, 0xFF, s);
+  if (flags & MC_STRICT) return strict_check(flags_out, n, (uint8_t)~MC_PF_EIGEN_FP64, s);
   return MC_OK;
 }
 

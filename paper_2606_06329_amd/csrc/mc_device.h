@@ -21,6 +21,7 @@ constexpr uint8_t PF_RANK_DEFICIENT = 4u;
 constexpr uint8_t PF_JACOBI_MAXSWEEPS = 8u;
 constexpr uint8_t PF_KNN_AMBIGUOUS = 16u;
 constexpr uint8_t PF_KNN_UNCERTIFIED = 32u;
+constexpr uint8_t PF_EIGEN_FP64 = 64u;
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 

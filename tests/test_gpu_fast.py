@@ -195,3 +195,31 @@ def test_fast_bf16_parity(name, n, m, k, seed, variant):
     print(f"bf16 {name} {variant}: max {err.max():.2e} median {np.median(err):.2e}")
     assert okr.mean() > 0.95
     assert err.max() <= TOL_LOW
+
+
+@pytest.mark.parametrize("variant", ["paper", "haar"])
+def test_fast_bf16_near_degenerate_refined(variant):
+    """bf16 moments take a float32 eigen-solve; a kept eigenvalue pair that is degenerate (here
+    exactly: the patch +-e1, +-e2, +-2 e3, +-3 e4 has equal variance along e1 and e2, and its
+    small integers are exact in bf16) is re-solved in float64 and flagged MC_PF_EIGEN_FP64.
+    Generic patches never take that path."""
+    import paper_2606_06329_amd as P
+    from paper_2606_06329_amd._lib import MC_PF_EIGEN_FP64
+    from tests.gpu_common import TOL_LOW
+    m, k = 256, 8
+    pts = np.zeros((k, m), np.float32)
+    for r, (ax, v) in enumerate([(0, 1), (1, 1), (2, 2), (3, 3)]):
+        pts[2 * r, ax], pts[2 * r + 1, ax] = v, -v
+    X = np.vstack([pts + np.float32(8.0),
+                   np.random.default_rng(8).standard_normal((24, m)).astype(np.float32)])
+    idx = np.tile(np.arange(k, dtype=np.int32), (X.shape[0], 1))
+    kap, fl = P.curvature_fast(to_dev(X), to_dev_idx(idx), variant, "bf16")
+    kap, fl = kap.cpu().numpy(), fl.cpu().numpy()
+    assert np.all(fl & MC_PF_EIGEN_FP64)
+    want, pe = oracle_fast(X, idx, variant, rows=np.array([0]))
+    assert pe[0] == 4
+    assert rel_err(kap[0], want[0]) <= TOL_LOW
+    # a generic bf16 workload stays on the float32 eigen-solve
+    Xc, idc = _case("clusters", 900, 784, 2061, 11)
+    _, flc = P.curvature_fast(to_dev(Xc), to_dev_idx(idc), variant, "bf16")
+    assert not np.any(flc.cpu().numpy() & MC_PF_EIGEN_FP64)

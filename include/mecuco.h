@@ -83,7 +83,7 @@ extern "C" {
 #define MC_PF_JACOBI_MAXSWEEPS 8u /* k x k eigen-solve hit its sweep limit */
 #define MC_PF_KNN_AMBIGUOUS 16u  /* k-th and (k+1)-th distances within float32 rounding of each other */
 #define MC_PF_KNN_UNCERTIFIED 32u /* the candidate set could not be proven to contain the k nearest */
-#define MC_PF_EIGEN_FP64 64u     /* (information) bf16 Fast mode: the float32 eigen-solve found a
+#define MC_PF_EIGEN_FP64 64u     /* (information) Fast mode: the float32 eigen-solve found a
                                     near-degenerate kept eigenvalue pair and was redone in float64 */
 
 /* operations for mc_workspace_bytes */
@@ -136,10 +136,10 @@ int mc_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int32_t k, int32_t
  *                give kappa = NaN and MC_PF_NONFINITE for that point
  *   k            2 <= k <= MC_KMAX
  *   precision    MC_FP32 | MC_BF16 | MC_FP64 (patch moments on MFMA; the
- *                combination is float64 in all three, the k x k eigen-solve float64
- *                Jacobi for MC_FP32 and MC_FP64 and float32 Jacobi for MC_BF16,
- *                redone in float64 when a kept eigenvalue pair is near-degenerate,
- *                flag MC_PF_EIGEN_FP64).  MC_FP64 centres
+ *                combination is float64 in all three; the k x k eigen-solve is
+ *                float32 Jacobi for MC_FP32 and MC_BF16, redone in float64 when a
+ *                kept eigenvalue pair is near-degenerate (flag MC_PF_EIGEN_FP64),
+ *                and float64 Jacobi for MC_FP64).  MC_FP64 centres
  *                and accumulates in float64 (v_mfma_f64_16x16x4f64): use it for
  *                thin or noisy patches whose Gram matrix is ill-conditioned, where
  *                float32 moments lose digits.  k > MC_FAST_FP64_KMAX -> MC_ESHAPE

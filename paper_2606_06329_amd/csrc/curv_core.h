@@ -307,10 +307,11 @@ __device__ int jacobi_sweeps(const PointLds& P, JT* JA, JT* JV, int k, int tg, J
 // k x k eigen-solve of the Gram matrix K.  On entry JA holds K (float64, k x k, zero-padded
 // to KK) and JV the identity.
 //  * F32 = false: float64 Jacobi sweeps to a relative 2^-52.
-//  * F32 = true (bf16 moments): float32 sweeps to 2^-23 on a float32 copy held in the JV
-//    storage.  Their eigenvalue error, about 2^-23 sigma_1, is far below that of the bf16
-//    moments themselves.  A kept spectrum with a near-degenerate pair (|sigma_x - sigma_y| <
-//    2^-13 sigma_1) is re-solved in float64 from the untouched JA; misc[5] records that.
+//  * F32 = true (float32 and bf16 moments): float32 sweeps to 2^-23 on a float32 copy held
+//    in the JV storage.  Jacobi is accurate relative to its data, and the moments' own
+//    rounding (2^-24 sigma_1 and more for float32, 2^-9 sigma_1 for bf16) dominates the
+//    solve's.  A kept spectrum with a near-degenerate pair (|sigma_x - sigma_y| < 2^-13
+//    sigma_1) is re-solved in float64 from the untouched JA; misc[5] records that.
 // On return: eigen order in P.ord, sig0 = sigma_1, pe = numerical rank (eigenvalues above
 // max(k, m) * unit * sigma_1 among the first min(k-1, m)), sweep = sweeps used, and
 // P.UT = U_p diag(sigma_p^(-1/2)).
@@ -660,7 +661,7 @@ __device__ uint8_t patch_front(const PointLds& P, const float* __restrict__ X, i
   tauk = P.RED[15 * C::NW];
   if (misc[1]) return PF_NONFINITE;
 
-  // ---- k x k eigen-solve (Jacobi; float32 sweeps for bf16 moments) on K --------------
+  // ---- k x k eigen-solve (Jacobi: float32 sweeps unless the moments are float64) on K --
   {
     constexpr int KK = C::KK;
     const MomT<PREC>* Krow = mom + (k + 1) * C::NPAD;
@@ -670,7 +671,7 @@ __device__ uint8_t patch_front(const PointLds& P, const float* __restrict__ X, i
       JV[x * C::JLD + y] = (x == y) ? 1.0 : 0.0;
     }
   }
-  jacobi_eigen<KMAX, C, PREC == MOM_BF16>(P, k, m, tg, PREC == MOM_FP64 ? 0x1p-44 : 0x1p-24, sig0, pe, sweep);
+  jacobi_eigen<KMAX, C, PREC != MOM_FP64>(P, k, m, tg, PREC == MOM_FP64 ? 0x1p-44 : 0x1p-24, sig0, pe, sweep);
   gsync<C::NW>();
   return 0;
 }

@@ -457,7 +457,7 @@ __global__ __launch_bounds__((Fast2CfgSel<KMAX, PREC>::C::NT)) void curv_fast2_k
   // ---- eigen-solve: Ut = U_p diag(sigma_p^(-1/2)) ------------------------------------
   double sig0;
   int pe, sweep;
-  jacobi_eigen<KMAX, C, PREC == MOM_BF16>(P, k, m, tg, PREC == MOM_FP64 ? 0x1p-44 : 0x1p-24, sig0, pe, sweep);
+  jacobi_eigen<KMAX, C, PREC != MOM_FP64>(P, k, m, tg, PREC == MOM_FP64 ? 0x1p-44 : 0x1p-24, sig0, pe, sweep);
   const int plim = (int)((int64_t)(k - 1) < m ? (int64_t)(k - 1) : m);
   uint8_t fl = 0;
   if (pe < plim) fl |= PF_RANK_DEFICIENT;

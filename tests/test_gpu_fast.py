@@ -52,6 +52,7 @@ def test_fast_fp32_parity(case, variant):
     rank_ok = (fl & 4) == 0
     rank_ok &= pe == min(k - 1, X.shape[1])
     err = rel_err(kap, want)
+    print(f"  max rel err {err[rank_ok].max():.2e}, median {np.median(err[rank_ok]):.2e}", flush=True)
     assert np.all(np.isfinite(kap))
     assert rank_ok.mean() > 0.95
     assert err[rank_ok].max() <= TOL_FP32, (err.max(), np.argmax(err))

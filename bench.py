@@ -183,6 +183,7 @@ def suite(args):
                     "stages_ms": {a: round(v[0] / v[1], 4) for a, v in st.items()},
                     "error_vs_oracle": errors_vs_oracle(kap_o, idx.cpu().numpy(), kap.cpu().numpy(),
                                                         fl.cpu().numpy()),
+                    "eigen_fp64_points": int(((fl.cpu().numpy() & 64) != 0).sum()),
                     "oracle_s_per_point_1core": round(t_or, 4)}
             if name == "swissroll":
                 # forward + adjoint of sum_i w_i kappa_i, neighbour lists fixed
@@ -354,7 +355,8 @@ def main():
         "stages_ms": {s: round(v[0] / v[1], 4) for s, v in stages.items()},
         "flags": {"rank_deficient": int(((fl_np & 4) != 0).sum()),
                   "knn_uncertified": int(((fl_np & 32) != 0).sum()),
-                  "knn_ambiguous": int(((fl_np & 16) != 0).sum())},
+                  "knn_ambiguous": int(((fl_np & 16) != 0).sum()),
+                  "eigen_fp64": int(((fl_np & 64) != 0).sum())},
     }
     kap_o = None
     if not args.no_cpu_baseline:

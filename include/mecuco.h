@@ -83,8 +83,8 @@ extern "C" {
 #define MC_PF_JACOBI_MAXSWEEPS 8u /* k x k eigen-solve hit its sweep limit */
 #define MC_PF_KNN_AMBIGUOUS 16u  /* k-th and (k+1)-th distances within float32 rounding of each other */
 #define MC_PF_KNN_UNCERTIFIED 32u /* the candidate set could not be proven to contain the k nearest */
-#define MC_PF_EIGEN_FP64 64u     /* (information) Fast mode: the float32 eigen-solve found a
-                                    near-degenerate kept eigenvalue pair and was redone in float64 */
+#define MC_PF_EIGEN_FP64 64u     /* (information) Fast mode: the float32 eigen-solve found two kept
+                                    eigenvalues within a relative 2^-13 and was redone in float64 */
 
 /* operations for mc_workspace_bytes */
 #define MC_OP_KNN 0

@@ -310,8 +310,9 @@ __device__ int jacobi_sweeps(const PointLds& P, JT* JA, JT* JV, int k, int tg, J
 //  * F32 = true (float32 and bf16 moments): float32 sweeps to 2^-23 on a float32 copy held
 //    in the JV storage.  Jacobi is accurate relative to its data, and the moments' own
 //    rounding (2^-24 sigma_1 and more for float32, 2^-9 sigma_1 for bf16) dominates the
-//    solve's.  A kept spectrum with a near-degenerate pair (|sigma_x - sigma_y| < 2^-13
-//    sigma_1) is re-solved in float64 from the untouched JA; misc[5] records that.
+//    solve's.  A kept spectrum with a near-degenerate pair (sigma_x, sigma_y within a
+//    relative 2^-13 of each other) is re-solved in float64 from the untouched JA; misc[5]
+//    records that.
 // On return: eigen order in P.ord, sig0 = sigma_1, pe = numerical rank (eigenvalues above
 // max(k, m) * unit * sigma_1 among the first min(k-1, m)), sweep = sweeps used, and
 // P.UT = U_p diag(sigma_p^(-1/2)).
@@ -349,7 +350,7 @@ __device__ void jacobi_eigen(const PointLds& P, int k, int64_t m, int tg, double
         if (lx > keep) {
           for (int y = 0; y < k; ++y) {
             const float ly = A32[y * C::JLD + y];
-            near |= y != tg && ly > keep && fabsf(lx - ly) < 0x1p-13f * s1;
+            near |= y != tg && ly > keep && fabsf(lx - ly) < 0x1p-13f * fmaxf(lx, ly);
           }
         }
       }

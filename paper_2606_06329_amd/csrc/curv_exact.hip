@@ -175,39 +175,102 @@ __global__ __launch_bounds__(256) void curv_exact_kernel(
     __syncthreads();
   }
   // ---- null columns: w_l = e_l - Y z_l, z_l = T y_l,  t_null^W = sum_l ||X_c (w_l o w_l)||^2 ----------
+  // Two float64 MFMA products per block of 16 null columns: D = Y Z_blk over 16-row blocks of
+  // a (K = pe, padded to 4 KS1), W2 = (E - D)^2 in registers, then acc += X_c W2 (K = the
+  // block's 16 rows).  The 16x16x4 f64 product leaves lane l holding rows l/16 + 4r of column
+  // l%16, which is exactly the B operand of the r-th K-step of the second product, so W2
+  // never leaves the registers.  Each wave takes NCB column blocks at once (blocks
+  // 4 (NCB g + c) + w): they share every Y and X_c operand, and their MFMA chains are
+  // independent.  Operands are read at clamped (always valid) LDS addresses and masked.
+  constexpr int KS1 = (KMAX + 3) / 4;          // K-steps over the reflectors
+  constexpr int JT = (KMAX + 15) / 16;         // 16-row tiles of X_c
+  constexpr int NCB = 4;                       // column blocks per wave and pass
+  const int lane = tg % WAVE, wid = tg / WAVE;
+  const int li = lane % 16, lq = lane / 16;
+  const int mm = (int)m;                       // m * pe values fit the LDS, so int indices
+  const int pp = pe;
+  const int ncb = (mm - pp + 15) / 16, nrb = (mm + 15) / 16;
   double tnull = 0.0;
-  for (int64_t l = pe + tg; l < m; l += 256) {
-    double z[KMAX];
+  for (int g0 = 0; g0 * 4 * NCB < ncb; ++g0) {
+    int ln[NCB];
+    double zb[NCB][KS1];
+    doublex4 acc2[NCB][JT];
 #pragma unroll
-    for (int s = 0; s < KMAX; ++s) {
-      double t = 0.0;
-      if (s < pe)
-        for (int u = s; u < pe; ++u) t = fma(Tf[s * KMAX + u], Vd[l * pe + u], t);   // y_l = row l of Y
-      z[s] = t;
+    for (int c = 0; c < NCB; ++c) {
+      const int cb = 4 * (NCB * g0 + c) + wid;
+      ln[c] = pp + 16 * cb + li;                 // null column of this lane's B operands
+      const int lnc = ln[c] < mm ? ln[c] : mm - 1;
+      // z_l[s] = sum_{u >= s} T[s][u] y_l[u], y_l = row l of Y (below the diagonal: l >= pe > u)
+#pragma unroll
+      for (int st = 0; st < KS1; ++st) {
+        const int sidx = 4 * st + lq;
+        double t = 0.0;
+        if (sidx < pp && ln[c] < mm)
+          for (int u = sidx; u < pp; ++u) t = fma(Tf[sidx * KMAX + u], Vd[lnc * pp + u], t);
+        zb[c][st] = t;
+      }
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt) acc2[c][jt] = doublex4{0.0, 0.0, 0.0, 0.0};
     }
-    double acc[KMAX];
+    for (int rb = 0; rb < nrb; ++rb) {
+      const int a0 = 16 * rb;
+      // A operands of the first product: Y[a0 + li][4 st + lq]
+      double yv[KS1];
+      {
+        const int a = a0 + li, ac = a < mm ? a : mm - 1;
 #pragma unroll
-    for (int j = 0; j < KMAX; ++j) acc[j] = 0.0;
-    for (int64_t a = 0; a < m; ++a) {
-      // Y[a][s]: 0 for a < s, 1 for a == s, Vd[a][s] below the diagonal
-      double yz = 0.0;
-#pragma unroll
-      for (int s = 0; s < KMAX; ++s) {
-        if (s < pe) {
-          const double y = a > s ? Vd[a * pe + s] : (a == s ? 1.0 : 0.0);
-          yz = fma(y, z[s], yz);
+        for (int st = 0; st < KS1; ++st) {
+          const int sidx = 4 * st + lq, sc = sidx < pp ? sidx : pp - 1;
+          const double raw = Vd[ac * pp + sc];
+          yv[st] = (sidx < pp && a < mm) ? (a > sidx ? raw : (a == sidx ? 1.0 : 0.0)) : 0.0;
         }
       }
-      const double wa = (a == l ? 1.0 : 0.0) - yz;
-      const double w2 = wa * wa;
-      const double x0 = (double)Xs[a], ma = mu[a];
+      // A operands of the second product: X_c[16 jt + li][a0 + 4 r + lq]
+      double xa[4][JT];
 #pragma unroll
-      for (int j = 0; j < KMAX; ++j)
-        if (j < k) acc[j] = fma(((double)Xs[(int64_t)j * m + a] - x0) - ma, w2, acc[j]);
+      for (int r = 0; r < 4; ++r) {
+        const int ax = a0 + 4 * r + lq, axc = ax < mm ? ax : mm - 1;
+        const double x0 = (double)Xs[axc], mua = mu[axc];
+#pragma unroll
+        for (int jt = 0; jt < JT; ++jt) {
+          const int jj = 16 * jt + li, jc = jj < k ? jj : k - 1;
+          const double v = ((double)Xs[jc * mm + axc] - x0) - mua;
+          xa[r][jt] = (jj < k && ax < mm) ? v : 0.0;
+        }
+      }
+      // the NCB chains interleave step by step: D for every block, then W2, then X_c W2
+      doublex4 d[NCB];
+#pragma unroll
+      for (int c = 0; c < NCB; ++c) d[c] = doublex4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int st = 0; st < KS1; ++st)
+#pragma unroll
+        for (int c = 0; c < NCB; ++c) d[c] = mfma16x16x4f64(yv[st], zb[c][st], d[c]);
+      // W2 = (E - D)^2 on this lane's rows a0 + lq + 4 r of column ln[c]
+      double w2[NCB][4];
+#pragma unroll
+      for (int c = 0; c < NCB; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = a0 + lq + 4 * r;
+          double wa = (a == ln[c] ? 1.0 : 0.0) - d[c][r];
+          if (a >= mm || ln[c] >= mm) wa = 0.0;
+          w2[c][r] = wa * wa;
+        }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int jt = 0; jt < JT; ++jt)
+#pragma unroll
+          for (int c = 0; c < NCB; ++c) acc2[c][jt] = mfma16x16x4f64(xa[r][jt], w2[c][r], acc2[c][jt]);
     }
+    // rows past k and columns past m are zero
 #pragma unroll
-    for (int j = 0; j < KMAX; ++j)
-      if (j < k) tnull = fma(acc[j], acc[j], tnull);
+    for (int c = 0; c < NCB; ++c)
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tnull = fma(acc2[c][jt][r], acc2[c][jt][r], tnull);
   }
   tnull = block_sum256(tnull, red);
 

@@ -54,8 +54,10 @@ __global__ __launch_bounds__(256) void knn_colsum_kernel(const float* __restrict
 // Column means from the partial sums: a block takes 16 columns, its 256 threads take 16
 // partial sums each (16 groups), then the groups are added in a fixed order (deterministic).
 __global__ __launch_bounds__(256) void knn_mean_kernel(const double* __restrict__ part, int64_t m,
-                                                       int nparts, int64_t n, float* __restrict__ mu) {
+                                                       int nparts, int64_t n, float* __restrict__ mu,
+                                                       uint32_t* __restrict__ stats) {
   __shared__ double red[16][17];
+  if (blockIdx.x == 0 && threadIdx.x < 2) stats[threadIdx.x] = 0u;   // for knn_stats' atomic maxima
   const int cl = threadIdx.x % 16, grp = threadIdx.x / 16;
   const int64_t c = (int64_t)blockIdx.x * 16 + cl;
   double s = 0.0;
@@ -119,13 +121,15 @@ __global__ __launch_bounds__(256) void knn_center_kernel(
   }
 }
 
-// stats[0] = max_i sqrt(norm_i), stats[1] = max_i radius_i  (one workgroup)
+// stats[0] = max_i sqrt(norm_i), stats[1] = max_i radius_i: every workgroup reduces a strided
+// share of the rows, then one atomic maximum per value (both are non-negative, so their
+// float32 bit patterns order like the values; knn_mean zeroes them first)
 __global__ __launch_bounds__(256) void knn_stats_kernel(const float* __restrict__ norms,
                                                         const float* __restrict__ radius, int64_t n,
-                                                        float* __restrict__ stats) {
+                                                        uint32_t* __restrict__ stats) {
   __shared__ float red[2][4];
   float a = 0.0f, b = 0.0f;
-  for (int64_t r = threadIdx.x; r < n; r += 256) {
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (int64_t)gridDim.x * 256) {
     a = fmaxf(a, sqrtf(norms[r]));
     b = fmaxf(b, radius[r]);
   }
@@ -137,8 +141,8 @@ __global__ __launch_bounds__(256) void knn_stats_kernel(const float* __restrict_
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    stats[0] = fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3]));
-    stats[1] = fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3]));
+    atomicMax(stats, __float_as_uint(fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3]))));
+    atomicMax(stats + 1, __float_as_uint(fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3]))));
   }
 }
 
@@ -947,18 +951,24 @@ __global__ __launch_bounds__(256) void knn_rerank_kernel(
   // list segments: row side (slots 0 ..), column side (slots slotb ..)
   const int64_t na = segments(a_start(S, qt), a_len(S, qt), GA, a_pairs(S));
   const int64_t nb = sym ? segments(b_start(S, qt), b_len(S, qt), GB, b_pairs(S)) : 0;
-  // merge the segment lists (each ascending; read in reverse, so descending) into the 64 best
+  // merge the segment lists (each ascending; read in reverse, so descending) into the 64 best;
+  // eight lists' loads are in flight before their merges
   uint32_t lh = KEY_PAD_HI, ll = KEY_PAD_LO;
-  for (int64_t sg = 0; sg < na + nb; ++sg) {
-    const int64_t slot = sg < na ? sg : slotb + (sg - na);
-    const int64_t o = ((qt * nslot + slot) * KBQ + row) * kc;
-    uint32_t bh = 0xFFFFFFFFu, bl = 0xFFFFFFFFu;
-    const int src = WAVE - 1 - lane;
-    if (src < kc) {
-      bh = f2ord(cand_s[o + src]);
-      bl = (uint32_t)cand_j[o + src];
+  const int src = WAVE - 1 - lane;
+  for (int64_t s0 = 0; s0 < na + nb; s0 += 8) {
+    uint32_t bh[8], bl[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t sg = s0 + u;
+      const int64_t slot = sg < na ? sg : slotb + (sg - na);
+      const int64_t o = ((qt * nslot + slot) * KBQ + row) * kc;
+      const bool in = sg < na + nb && src < kc;
+      bh[u] = in ? f2ord(cand_s[o + src]) : 0xFFFFFFFFu;
+      bl[u] = in ? (uint32_t)cand_j[o + src] : 0xFFFFFFFFu;
     }
-    wave_merge64(lh, ll, bh, bl);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (s0 + u < na + nb) wave_merge64(lh, ll, bh[u], bl[u]);
   }
   const int lj = (int)ll;
   const float s_last = ord2f(rdlane_u(lh, kc - 1));   // every non-candidate scores >= s_last
@@ -1164,7 +1174,7 @@ hipError_t launch_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int k, 
   timing_end(0, stream);
   timing_begin(1, stream);
   hipLaunchKernelGGL(knn_mean_kernel, dim3((unsigned)((m + 15) / 16)), dim3(256), 0, stream, part, m,
-                     (int)parts, n, mu);
+                     (int)parts, n, mu, reinterpret_cast<uint32_t*>(stats));
   timing_end(1, stream);
   timing_begin(2, stream);
   uint32_t* thr = reinterpret_cast<uint32_t*>(base + plan.off_thr);
@@ -1172,7 +1182,9 @@ hipError_t launch_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int k, 
                      m, ldx, mp, mu, xc, scales, norms, radius, precision, thr);
   timing_end(2, stream);
   timing_begin(3, stream);
-  hipLaunchKernelGGL(knn_stats_kernel, dim3(1), dim3(256), 0, stream, norms, radius, n, stats);
+  const unsigned sgrid = (unsigned)((n + 255) / 256 < 64 ? (n + 255) / 256 : 64);
+  hipLaunchKernelGGL(knn_stats_kernel, dim3(sgrid), dim3(256), 0, stream, norms, radius, n,
+                     reinterpret_cast<uint32_t*>(stats));
   timing_end(3, stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

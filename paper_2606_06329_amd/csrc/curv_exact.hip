@@ -99,6 +99,54 @@ __global__ __launch_bounds__(256) void curv_exact_kernel(
   auto xcen = [&](int j, int64_t a) -> double {
     return ((double)Xs[(int64_t)j * m + a] - (double)Xs[a]) - mu[a];
   };
+  const int lane = tg % WAVE, wid = tg / WAVE;
+  const int li = lane % 16, lq = lane / 16;
+  const int mm = (int)m;                       // m * pe values fit the LDS, so int indices
+  const int pp = pe;
+  // the staged-chunk / moment storage of patch_front is free from here on: small products
+  // and reductions go there
+  constexpr int MT = (KMAX + 15) / 16;         // 16-wide tiles of a KMAX-sized index
+  constexpr int SLD = 16 * MT;                 // row stride of a small product in scr
+  static_assert(C::U0_B >= sizeof(double) * SLD * SLD, "scratch for the small products");
+  static_assert(C::U0_B >= sizeof(double) * 4 * KMAX, "scratch for the vector reductions");
+  double* scr = reinterpret_cast<double*>(P.lhs);
+  // scr[i][n] = sum_{a < m} fa(i, a) fb(n, a) for i, n < SLD on float64 MFMA: wave w takes the
+  // K-steps a0 = 16 t + 4 w (lane l supplies A[l%16][l/16] and B[l/16][l%16]), and the four
+  // partial products are added in wave order (deterministic).  fa, fb are 0 out of range.
+  auto small_product = [&](auto fa, auto fb) {
+    doublex4 acc[MT][MT];
+#pragma unroll
+    for (int ti = 0; ti < MT; ++ti)
+#pragma unroll
+      for (int tn = 0; tn < MT; ++tn) acc[ti][tn] = doublex4{0.0, 0.0, 0.0, 0.0};
+    for (int a0 = 4 * wid; a0 < mm; a0 += 16) {
+      const int a = a0 + lq;
+      double av[MT], bv[MT];
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        av[t] = a < mm ? fa(16 * t + li, a) : 0.0;
+        bv[t] = a < mm ? fb(16 * t + li, a) : 0.0;
+      }
+#pragma unroll
+      for (int ti = 0; ti < MT; ++ti)
+#pragma unroll
+        for (int tn = 0; tn < MT; ++tn) acc[ti][tn] = mfma16x16x4f64(av[ti], bv[tn], acc[ti][tn]);
+    }
+    for (int w = 0; w < 4; ++w) {
+      if (wid == w) {
+#pragma unroll
+        for (int ti = 0; ti < MT; ++ti)
+#pragma unroll
+          for (int tn = 0; tn < MT; ++tn)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              double& cell = scr[(16 * ti + lq + 4 * r) * SLD + 16 * tn + li];
+              cell = (w == 0 ? 0.0 : cell) + acc[ti][tn][r];
+            }
+      }
+      __syncthreads();
+    }
+  };
   // ---- V_r = X_c^T Ut (float64), and t_range = ||X_c V_r^{o2}||^2 ------------------------
   for (int64_t e = tg; e < m * pe; e += 256) {
     const int64_t a = e / pe;
@@ -108,24 +156,49 @@ __global__ __launch_bounds__(256) void curv_exact_kernel(
     Vd[a * pe + l] = s;
   }
   __syncthreads();
+  small_product([&](int i, int a) { return i < k ? xcen(i, a) : 0.0; },
+                [&](int n, int a) {
+                  const double v = n < pp ? Vd[a * pp + n] : 0.0;
+                  return v * v;
+                });
   double trange = 0.0;
   for (int e = tg; e < k * pe; e += 256) {
-    const int j = e / pe, l = e % pe;
-    double s = 0.0;
-    for (int64_t a = 0; a < m; ++a) {
-      const double v = Vd[a * pe + l];
-      s = fma(xcen(j, a), v * v, s);
-    }
-    trange = fma(s, s, trange);
+    const double v = scr[(e / pe) * SLD + e % pe];
+    trange = fma(v, v, trange);
   }
   trange = block_sum256(trange, red);
 
   // ---- Householder QR of V_r in place (LAPACK geqr2 / dlarfg convention) --------------------
+  // Step j: one pass gives ||x||^2 (c = j) and the column products dots[c] = sum_{a > j}
+  // V[a][j] V[a][c] (c > j) of the unscaled reflector, one vector reduction sums them, and
+  // with v = scal V[:, j] (v_j = 1) the update is V[:, c] -= tau (V[j][c] + scal dots[c]) v.
   for (int j = 0; j < pe; ++j) {
-    double ss = 0.0;
-    for (int64_t a = j + 1 + tg; a < m; a += 256) ss = fma(Vd[a * pe + j], Vd[a * pe + j], ss);
-    const double xnorm2 = block_sum256(ss, red);
-    const double alpha = Vd[(int64_t)j * pe + j];
+    double part[KMAX], vjc[KMAX];
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) part[c] = 0.0;
+    for (int a = j + 1 + tg; a < mm; a += 256) {
+      const double vj = Vd[a * pp + j];
+#pragma unroll
+      for (int c = 0; c < KMAX; ++c)
+        if (c >= j && c < pp) part[c] = fma(vj, Vd[a * pp + c], part[c]);
+    }
+    // V[j][c] before the reduction's barriers: thread 0 rewrites the row below
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) vjc[c] = (c > j && c < pp) ? Vd[j * pp + c] : 0.0;
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) {
+      const double ws = (c >= j && c < pp) ? wave_sum(part[c]) : 0.0;
+      if (lane == 0) scr[wid * KMAX + c] = ws;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c)
+      part[c] = (scr[c] + scr[KMAX + c]) + (scr[2 * KMAX + c] + scr[3 * KMAX + c]);
+    const double alpha = Vd[j * pp + j];
+    __syncthreads();   // everyone has read scr and alpha
+    double xnorm2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) xnorm2 = c == j ? part[c] : xnorm2;
     double tauj = 0.0, scal = 0.0, beta = alpha;
     if (xnorm2 > 0.0) {
       const double nrm = sqrt(alpha * alpha + xnorm2);
@@ -133,38 +206,37 @@ __global__ __launch_bounds__(256) void curv_exact_kernel(
       tauj = (beta - alpha) / beta;
       scal = 1.0 / (alpha - beta);
     }
-    __syncthreads();
+    double f[KMAX];
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) f[c] = (c > j && c < pp) ? tauj * (vjc[c] + scal * part[c]) : 0.0;
     if (tauj != 0.0) {
-      for (int64_t a = j + 1 + tg; a < m; a += 256) Vd[a * pe + j] *= scal;   // v below the diagonal
+      for (int a = j + 1 + tg; a < mm; a += 256) {
+        const double va = Vd[a * pp + j] * scal;   // v below the diagonal
+        Vd[a * pp + j] = va;
+#pragma unroll
+        for (int c = 0; c < KMAX; ++c)
+          if (c > j && c < pp) Vd[a * pp + c] -= f[c] * va;
+      }
     }
     if (tg == 0) {
-      Vd[(int64_t)j * pe + j] = beta;
+      Vd[j * pp + j] = beta;
       tau_h[j] = tauj;
+#pragma unroll
+      for (int c = 0; c < KMAX; ++c)
+        if (c > j && c < pp) Vd[j * pp + c] = vjc[c] - f[c];
     }
     __syncthreads();
-    // apply H_j = I - tau v v^T (v_j = 1) to columns j+1 .. pe-1
-    for (int c = j + 1; c < pe; ++c) {
-      double d = 0.0;
-      for (int64_t a = j + 1 + tg; a < m; a += 256) d = fma(Vd[a * pe + j], Vd[a * pe + c], d);
-      // read V[j][c] before the reduction's barriers: thread 0 rewrites it right after them
-      const double vjc = Vd[(int64_t)j * pe + c];
-      d = block_sum256(d, red) + vjc;
-      const double f = tauj * d;
-      if (tg == 0) Vd[(int64_t)j * pe + c] -= f;
-      for (int64_t a = j + 1 + tg; a < m; a += 256) Vd[a * pe + c] -= f * Vd[a * pe + j];
-      __syncthreads();
-    }
   }
   // ---- compact WY factor T (LAPACK dlarft, forward, columnwise) -----------------------------
-  // Y[:, j] = (0..0, 1, Vd[j+1:, j]);  T[j][j] = tau_j;  T[0:j, j] = -tau_j T[0:j, 0:j] (Y^T y_j)[0:j]
+  // Y[:, j] = (0..0, 1, Vd[j+1:, j]);  T[j][j] = tau_j;  T[0:j, j] = -tau_j T[0:j, 0:j] (Y^T y_j)[0:j],
+  // with the Gram Y^T Y from one float64 MFMA product
+  auto yval = [&](int s, int a) -> double {
+    if (s >= pp) return 0.0;
+    return a > s ? Vd[a * pp + s] : (a == s ? 1.0 : 0.0);
+  };
+  small_product(yval, yval);
   for (int j = 0; j < pe; ++j) {
-    for (int s = 0; s < j; ++s) {
-      // (Y^T y_j)[s] = sum_a Y[a][s] Y[a][j] = Y[j][s] + sum_{a>j} Y[a][s] Y[a][j]
-      double d = 0.0;
-      for (int64_t a = j + 1 + tg; a < m; a += 256) d = fma(Vd[a * pe + s], Vd[a * pe + j], d);
-      d = block_sum256(d, red) + Vd[(int64_t)j * pe + s];
-      if (tg == 0) wv[s] = -tau_h[j] * d;
-    }
+    if (tg < j) wv[tg] = -tau_h[j] * scr[tg * SLD + j];
     __syncthreads();
     if (tg < j) {
       double t = 0.0;
@@ -185,10 +257,6 @@ __global__ __launch_bounds__(256) void curv_exact_kernel(
   constexpr int KS1 = (KMAX + 3) / 4;          // K-steps over the reflectors
   constexpr int JT = (KMAX + 15) / 16;         // 16-row tiles of X_c
   constexpr int NCB = 4;                       // column blocks per wave and pass
-  const int lane = tg % WAVE, wid = tg / WAVE;
-  const int li = lane % 16, lq = lane / 16;
-  const int mm = (int)m;                       // m * pe values fit the LDS, so int indices
-  const int pp = pe;
   const int ncb = (mm - pp + 15) / 16, nrb = (mm + 15) / 16;
   double tnull = 0.0;
   for (int g0 = 0; g0 * 4 * NCB < ncb; ++g0) {

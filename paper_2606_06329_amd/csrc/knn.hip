@@ -11,10 +11,17 @@
 //  2. knn_gemm_topk: query tile x database tile scores s = ||y||^2 - 2 x.y on
 //     MFMA (fp32 32x32x2, bf16 16x16x32 or fp8 16x16x32), written to LDS; each
 //     wave keeps a sorted 64-entry list of (score, index) per query row across
-//     its lanes, filters every row against its K'-th entry with a ballot and
-//     takes in survivors by a DPP shift (few) or a bitonic sort and merge (many).
-//     The tile-pair grid is cut into equal contiguous ranges, one per workgroup.
-//  3. knn_rerank: merge the range segments, recompute the K' distances in float32
+//     its lanes, filters every row against its K'-th entry (and the smallest one
+//     any workgroup has published for that query) with a ballot and takes in
+//     survivors by a DPP shift (few) or a bitonic sort and merge (many).  The
+//     list of tile pairs is cut into equal contiguous ranges, one per workgroup.
+//     The distance matrix is symmetric: under the symmetric schedule each
+//     unordered tile pair is scored once and its transposed scores go to the
+//     workspace for the other tile's queries.
+//  3. knn_rowcap / knn_column_topk (symmetric schedule): bound each query's final
+//     K'-th key by its merged row-side lists, then stream the transposed tiles
+//     through the same list code (the column side).
+//  4. knn_rerank: merge all list segments, recompute the K' distances in float32
 //     difference form sum_a (x_a - y_a)^2 from the original X, order by
 //     (distance, index), keep k, and flag ambiguous gaps and candidate sets
 //     that cannot be certified complete.

@@ -369,13 +369,12 @@ static hipError_t launch_bwd_k(const float* X, int64_t n, int64_t m, int64_t ldx
                                const int32_t* idx, int k, int variant, const float* gk,
                                float gap_eps, float* grad, hipStream_t stream) {
   using C = typename BwdCfgSel<KMAX>::C;
-  static bool attr_set = false;   // LDS beyond 64 KiB needs the opt-in attribute
-  if (!attr_set) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&curv_backward_kernel<KMAX>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::BYTES);
+  static std::atomic<uint64_t> attr_set{0};   // LDS beyond 64 KiB needs the opt-in attribute
+  once_per_device(attr_set, [] {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&curv_backward_kernel<KMAX>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::BYTES);
     (void)hipGetLastError();
-    attr_set = true;
-  }
+  });
   timing_begin(8, stream);
   hipLaunchKernelGGL(curv_backward_kernel<KMAX>, dim3((unsigned)n), dim3(C::NT), C::BYTES, stream, X,
                      n, m, ldx, idx, k, variant, gk, gap_eps, grad);

@@ -378,8 +378,8 @@ static hipError_t launch_exact_k(const float* X, int64_t n, int64_t m, int64_t l
                                  const int32_t* idx, int k, float* kappa, uint8_t* flags,
                                  hipStream_t stream) {
   const size_t lds = exact_lds_bytes<KMAX>(m, k);
-  hipFuncSetAttribute(reinterpret_cast<const void*>(&curv_exact_kernel<KMAX>),
-                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&curv_exact_kernel<KMAX>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   (void)hipGetLastError();
   timing_begin(7, stream);
   hipLaunchKernelGGL(curv_exact_kernel<KMAX>, dim3((unsigned)n), dim3(256), lds, stream, X, n, m, ldx,

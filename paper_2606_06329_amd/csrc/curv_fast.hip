@@ -672,12 +672,11 @@ static hipError_t launch_fast_kp(const float* X, int64_t n, int64_t m, int64_t l
   const void* fn;
   if constexpr (KMAX <= FAST1_KMAX) fn = reinterpret_cast<const void*>(&curv_fast1_kernel<KMAX, PREC>);
   else fn = reinterpret_cast<const void*>(&curv_fast2_kernel<KMAX, PREC>);
-  static bool attr_set = false;   // LDS beyond 64 KiB needs the opt-in attribute
-  if (!attr_set) {
+  static std::atomic<uint64_t> attr_set{0};   // LDS beyond 64 KiB needs the opt-in attribute
+  once_per_device(attr_set, [&] {
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(C::PPW * C::BYTES));
     (void)hipGetLastError();
-    attr_set = true;
-  }
+  });
   const unsigned grid = (unsigned)((n + C::PPW - 1) / C::PPW);
   timing_begin(6, stream);
   if constexpr (KMAX <= FAST1_KMAX) {

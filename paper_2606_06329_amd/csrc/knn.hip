@@ -1196,17 +1196,16 @@ hipError_t launch_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int k, 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
 
-  static bool attr_set = false;   // LDS beyond 64 KiB needs the opt-in attribute
-  if (!attr_set) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&knn_gemm_topk_kernel<0>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_lds_bytes<0>());
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&knn_gemm_topk_kernel<1>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_lds_bytes<1>());
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&knn_gemm_topk_kernel<2>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_lds_bytes<2>());
+  static std::atomic<uint64_t> attr_set{0};   // LDS beyond 64 KiB needs the opt-in attribute
+  once_per_device(attr_set, [] {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&knn_gemm_topk_kernel<0>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_lds_bytes<0>());
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&knn_gemm_topk_kernel<1>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_lds_bytes<1>());
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&knn_gemm_topk_kernel<2>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_lds_bytes<2>());
     (void)hipGetLastError();
-    attr_set = true;
-  }
+  });
   float* tbuf = reinterpret_cast<float*>(base + plan.off_tbuf);
   const int nslot = plan.smax + plan.smax_b;
   const int self = include_self ? 1 : 0;

@@ -5,9 +5,27 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include <hip/hip_runtime_api.h>
 
 namespace mc {
+
+// Runs the idempotent `fn` (e.g. a kernel attribute setter) once per device, keyed by the
+// current device's ordinal (< 64); thread-safe: concurrent first calls may both run it.
+template <class F>
+void once_per_device(std::atomic<uint64_t>& done, F fn) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    (void)hipGetLastError();
+    fn();
+    return;
+  }
+  const uint64_t bit = 1ull << dev;
+  if (done.load(std::memory_order_acquire) & bit) return;
+  fn();
+  done.fetch_or(bit, std::memory_order_release);
+}
 
 // Stage timers (mc_timing.cpp): no-ops unless mc_timing_enable(1) was called.
 void timing_begin(int stage, hipStream_t s);

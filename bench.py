@@ -169,10 +169,14 @@ def suite(args):
     import paper_2606_06329_amd as P
     from paper_2606_06329_amd import _lib, synth
 
-    plan = [("sphere", ("fp32",), True), ("torus", ("fp32", "bf16"), False),
-            ("swissroll", ("fp32",), False), ("blobs", ("fp32", "fp8"), False)]
-    for name, precs, with_exact in plan:
-        X, k = synth.make(name)
+    # (workload, precisions, exact mode too, n override, k override); the last entry is the
+    # cluster cloud at the paper's MNIST_784 shape (n = 70000, k = log2 n = 16), for context
+    plan = [("sphere", ("fp32",), True, None, None), ("torus", ("fp32", "bf16"), False, None, None),
+            ("swissroll", ("fp32",), False, None, None), ("blobs", ("fp32", "fp8"), False, None, None),
+            ("clusters", ("fp32", "bf16"), False, 70000, 16)]
+    for name, precs, with_exact, n_over, k_over in plan:
+        X, k = synth.make(name, n=n_over)
+        k = k_over or k
         n, m = X.shape
         Xd = torch.from_numpy(X).cuda()
         rows = np.random.default_rng(11).choice(n, min(n, 120 if m < 1000 else 40), replace=False)

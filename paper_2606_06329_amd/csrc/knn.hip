@@ -1095,11 +1095,12 @@ static int64_t knn_mp(int64_t m, int precision) {
   return ((m + bk - 1) / bk) * bk;
 }
 
-// Workgroups of a list stage over P tile pairs: about 2 per CU (register and LDS bound),
-// never fewer than the row tiles, a multiple of 8 for the XCD map.
+// Workgroups of a list stage over P tile pairs: 2 resident per CU (register and LDS bound),
+// so a whole number of 512-workgroup waves (no part-full last wave), never fewer than the
+// row tiles; a multiple of 8 for the XCD map.
 static int64_t knn_groups(int64_t P, int64_t T) {
-  int64_t G = 512;
-  if (G < T) G = T;
+  constexpr int64_t RESIDENT = 512;
+  int64_t G = (T + RESIDENT - 1) / RESIDENT * RESIDENT;
   if (G > P) G = P;
   if (G >= 8) G = (G + 7) / 8 * 8;
   if (G > P) G = P;

@@ -407,6 +407,27 @@ __device__ __forceinline__ void stage_store(const uint4 (&pre)[Stage<PREC>::NPRE
   }
 }
 
+// Branch-free stage_load for the prefetch behind the top-K' work: rows past n read row n - 1
+// (in bounds) instead of zeros, so no load sits behind a branch and every wait on the loads
+// issued before it counts exactly the memory operations issued after them.  Those rows only
+// reach query rows whose lists are never written or published and database columns the
+// score epilogue sets to +inf, whose transposed scores add the +inf norm of a row past n.
+template <int PREC>
+__device__ __forceinline__ void stage_load_clamped(uint4 (&pre)[Stage<PREC>::NPRE], const void* __restrict__ xsrc,
+                                                   int64_t mp, int64_t n, int64_t q0, int64_t j0) {
+  using S = Stage<PREC>;
+  const unsigned char* xs = reinterpret_cast<const unsigned char*>(xsrc);
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < S::NPRE; ++u) {
+    const int f = tid + u * KNT;
+    const int row = f / S::CPR, c = f % S::CPR;
+    int64_t g = row < KBQ ? q0 + row : j0 + (row - KBQ);
+    g = g < n ? g : n - 1;
+    pre[u] = *reinterpret_cast<const uint4*>(xs + g * mp * GemmCfg<PREC>::ESZ + 16 * c);
+  }
+}
+
 template <int PREC>
 constexpr size_t gemm_lds_bytes() {
   return Stage<PREC>::STAGE_B > (size_t)KBQ * SLD * 4 ? Stage<PREC>::STAGE_B
@@ -782,32 +803,51 @@ __global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     }
     const int64_t j0 = a_db(S, qt, d) * KBN;
     const int64_t q0 = qt * KBQ;
-    // lane rr < RPW: the smallest K'-th key any workgroup has published for row RPW w + rr
     const int64_t gq = q0 + RPW * w + lane;
-    const uint32_t capv = lane < RPW && gq < n ? thr[gq] : 0xFFFFFFFFu;
     tile_scores<PREC>(xsrc, mp, norms, scales, n, q0, j0, include_self, smem, pre);
     __syncthreads();
+    // Norms of the query rows (transposed store) and database columns (filter), then stage 0
+    // of the next pair, all unconditional (clamped rows): no later wait on memory before the
+    // next pair's first LDS store.
+    const int64_t nl = n - 1;
+    const float njr0 = norms[j0 + lane < n ? j0 + lane : nl];
+    const float njr1 = norms[j0 + 64 + lane < n ? j0 + 64 + lane : nl];
+    // lane rr < RPW: the smallest K'-th key any workgroup has published for row RPW w + rr,
+    // read after the pair's GEMM (the later, the smaller)
+    const uint32_t thrr = thr[gq < n ? gq : nl];
+    const float nxr0 = norms[q0 + lane < n ? q0 + lane : nl];
+    const float nxr1 = norms[q0 + 64 + lane < n ? q0 + 64 + lane : nl];
+    const float nx0 = q0 + lane < n ? nxr0 : INFINITY;
+    const float nx1 = q0 + 64 + lane < n ? nxr1 : INFINITY;
+    const float nj0 = j0 + lane < n ? njr0 : 0.0f;
+    const float nj1 = j0 + 64 + lane < n ? njr1 : 0.0f;
+    const uint32_t capv = lane < RPW && gq < n ? thrr : 0xFFFFFFFFu;
+    // an empty statement that takes these values completes their loads here, ahead of the
+    // stage load: a later wait for them (the store branch below is conditional) would also
+    // wait for the stage load and the transposed stores
+    __asm__ volatile("" ::"v"(nx0), "v"(nx1), "v"(nj0), "v"(nj1), "v"(capv));
+    __builtin_amdgcn_sched_barrier(0);
+    int64_t nqt = qt, nd = d;
+    a_next(S, nqt, nd);
+    if (t + 1 >= te) {   // last pair: reload this one (never used)
+      nqt = qt;
+      nd = d;
+    }
+    stage_load_clamped<PREC>(pre, xsrc, mp, n, nqt * KBQ, a_db(S, nqt, nd) * KBN);
     // the symmetric schedule's off-diagonal pairs leave the transposed scores for the column
     // pass: tbuf[pair][c][r] = ||x_r||^2 + D[r][c] (+inf past row n); wave w writes columns
     // 16 w .. 16 w + 15, lanes over rows
     if (sym && d > 0) {
-      float* tout = tbuf + b_index(S, qt, d) * (KBQ * KBN);
-      const float nx0 = q0 + lane < n ? norms[q0 + lane] : INFINITY;
-      const float nx1 = q0 + 64 + lane < n ? norms[q0 + 64 + lane] : INFINITY;
+      // the column base is wave-uniform (scalar address + 32-bit lane offset)
+      const int c0 = 16 * __builtin_amdgcn_readfirstlane(w);
+      float* tout = tbuf + b_index(S, qt, d) * (KBQ * KBN) + c0 * KBQ;
 #pragma unroll 4
       for (int cc = 0; cc < 16; ++cc) {
-        const int c = 16 * w + cc;
-        tout[c * KBQ + lane] = Ss[lane * SLD + c] + nx0;
-        tout[c * KBQ + 64 + lane] = Ss[(64 + lane) * SLD + c] + nx1;
+        tout[cc * KBQ + lane] = Ss[lane * SLD + c0 + cc] + nx0;
+        tout[cc * KBQ + 64 + lane] = Ss[(64 + lane) * SLD + c0 + cc] + nx1;
       }
     }
-    // stage 0 of the next tile is fetched now and lands behind the top-K' work below
-    int64_t nqt = qt, nd = d;
-    a_next(S, nqt, nd);
-    if (t + 1 < te) stage_load<PREC>(pre, xsrc, mp, n, nqt * KBQ, a_db(S, nqt, nd) * KBN, 0);
     const float* srow = Ss + RPW * w * SLD + lane;
-    const float nj0 = j0 + lane < n ? norms[j0 + lane] : 0.0f;
-    const float nj1 = j0 + 64 + lane < n ? norms[j0 + 64 + lane] : 0.0f;
     const auto score = [&](int rr, int h) { return srow[rr * SLD + 64 * h] + (h ? nj1 : nj0); };
     const uint32_t need = lists_filter(lh, score, kc, capv);
     lists_apply(lh, ll, need, score, (uint32_t)j0, kc, lane, capv);

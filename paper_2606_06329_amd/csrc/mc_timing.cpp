@@ -45,7 +45,11 @@ void timing_begin(int stage, hipStream_t s) {
   if (!g_on || stage < 0 || stage >= MC_STAGE_COUNT) return;
   hipEvent_t e = take();
   if (!e) return;
-  hipEventRecord(e, s);
+  if (hipEventRecord(e, s) != hipSuccess) {   // no timing for this launch; leave no error behind
+    (void)hipGetLastError();
+    g_pool.push_back(e);
+    return;
+  }
   g_pending[stage] = e;
   g_has_pending[stage] = true;
 }
@@ -54,10 +58,18 @@ void timing_end(int stage, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_on || stage < 0 || stage >= MC_STAGE_COUNT || !g_has_pending[stage]) return;
   hipEvent_t e = take();
-  if (!e) return;
-  hipEventRecord(e, s);
-  g_open.push_back(Rec{stage, g_pending[stage], e});
   g_has_pending[stage] = false;
+  if (!e) {
+    g_pool.push_back(g_pending[stage]);
+    return;
+  }
+  if (hipEventRecord(e, s) != hipSuccess) {
+    (void)hipGetLastError();
+    g_pool.push_back(g_pending[stage]);
+    g_pool.push_back(e);
+    return;
+  }
+  g_open.push_back(Rec{stage, g_pending[stage], e});
 }
 
 }  // namespace mc

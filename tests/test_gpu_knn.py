@@ -143,6 +143,25 @@ def test_knn_tile_counts(n):
     assert not np.any(idx == np.arange(n)[:, None])
 
 
+def test_knn_symmetric_schedule_max_n():
+    """n = 131072 (1024 tiles): the largest cloud the symmetric schedule takes, whose 523776
+    transposed tiles fill the 32 GiB limit (tile offsets past 2^32 floats); sets exact on
+    sampled rows, including both ends and tiles far apart in the schedule."""
+    import paper_2606_06329_amd as P
+    n = 131072
+    assert P.knn_symmetric(n) and not P.knn_symmetric(n + 1)
+    X = synth.swissroll(n=n, m=8, seed=4078)
+    k = 8
+    print(f"knn symmetric schedule n={n} m=8 k=8", flush=True)
+    idx, _, fl = P.knn(to_dev(X), k)
+    idx = idx.cpu().numpy()
+    rows = np.random.default_rng(7).choice(n, 200, replace=False)
+    rows = np.concatenate([rows, [0, 1, 127, 128, n // 2, n - 129, n - 128, n - 1]])
+    bad_big, bad_small, nbig, _ = knn_set_report(idx, X, rows, k)
+    print(f"  mismatches: {bad_big} (gap above bound, of {nbig}), {bad_small} (below)", flush=True)
+    assert bad_big == 0
+
+
 def test_knn_full_schedule_large_n():
     """n = 140000 (1094 tiles): past the symmetric schedule's workspace limit, so every tile
     pair is scored in both orders; sets exact on sampled rows."""

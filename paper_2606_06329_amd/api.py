@@ -133,9 +133,14 @@ def curvature_backward(X: torch.Tensor, idx: torch.Tensor, grad_kappa: torch.Ten
     k = idx.shape[1]
     _idx(idx, n, k, X.device)
     if grad_X is None:
-        grad_X = torch.zeros_like(X)
-    if grad_X.shape != X.shape or grad_X.stride() != X.stride() or grad_X.dtype != torch.float32:
-        raise ValueError("grad_X must match X in shape, stride and dtype")
+        # same row stride as X (a column slice of a wider matrix keeps its ldx)
+        grad_X = torch.zeros((n, ldx), dtype=torch.float32, device=X.device)[:, :m]
+    if (grad_X.shape != X.shape or grad_X.stride() != X.stride() or grad_X.dtype != torch.float32
+            or grad_X.device != X.device):
+        raise ValueError("grad_X must match X in shape, stride, dtype and device")
+    if not (isinstance(grad_kappa, torch.Tensor) and grad_kappa.device == X.device
+            and grad_kappa.dim() == 1 and grad_kappa.numel() == n):
+        raise ValueError(f"grad_kappa must be a length-{n} vector on X's device")
     gk = grad_kappa.contiguous().to(torch.float32)
     ws = _workspace(L.lib().mc_workspace_bytes(L.MC_OP_BACKWARD, n, m, k, L.MC_FP32, 1), X.device)
     st = L.lib().mc_curvature_backward(X.data_ptr(), n, m, ldx, idx.data_ptr(), k, _VAR[variant],

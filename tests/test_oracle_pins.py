@@ -284,3 +284,59 @@ def test_single_sign_flip_changes_kappa():
     b = oc.canonical_exact_kappa(Xf - Xf.mean(0))
     u = 0.5 * math.sin(2 * theta)
     assert abs((a - b) - 4 * u ** 3 * (v1 - v2)) <= 1e-12 * a
+
+
+def _two_point_closed_form(d):
+    """Every Fast-branch term of a two-point patch, derived by hand in exact rational arithmetic.
+
+    With k = 2 the centred rows are +d/2 and -d/2, p = 1 and V_r = d/|d|, so with
+    S1 = sum d_a, S3 = sum d_a^3, S4 = sum d_a^4 and D2 = |d|^2:
+      tau = t_S = D2/2,  t_range = g = (S3/D2)^2/2,  t_A = (S1 - S3/D2)^2/2,  t_D = S4/(2 D2);
+    the printed reading then has t_null = (t_A + 2 (g - tau))/q and the Haar reading
+    t_null = (t_A + 2 (tau - 2 t_D + g))/(q + 2), q = m - 1 (Fast branch of Algorithm 1,
+    eqs. tA, tB, tnull and gnull_exp)."""
+    from fractions import Fraction as F
+    d = [F(int(x)) for x in d]
+    m = len(d)
+    D2 = sum(x * x for x in d)
+    S1 = sum(d)
+    S3 = sum(x ** 3 for x in d)
+    S4 = sum(x ** 4 for x in d)
+    tau = D2 / 2
+    t_range = (S3 / D2) ** 2 / 2
+    g = t_range
+    t_A = (S1 - S3 / D2) ** 2 / 2
+    t_D = S4 / (2 * D2)
+    q = m - 1
+    t_null_p = (t_A + 2 * (tau - 2 * tau + g)) / q
+    t_null_h = (t_A + 2 * (tau - 2 * t_D + g)) / (q + 2)
+    kp = abs((t_range + t_null_p) / 2 + tau / 2)
+    kh = abs((t_range + t_null_h) / 2 + tau / 2)
+    return dict(tau=tau, t_range=t_range, g=g, t_A=t_A, t_S=tau, t_D=t_D, kappa_paper=kp, kappa_haar=kh)
+
+
+@pytest.mark.parametrize("d,kp,kh", [
+    ((1, 2, 2, 0, 0), "497/162", "215/54"),
+    ((3, -1, 2, 0, 0, 0, 0, 1, 0, 0, 0), None, None),
+    ((2, 1, 0, 0, -2, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 4, 0, 0), None, None),
+])
+def test_two_point_closed_form(d, kp, kh):
+    """The Fast branch's null-space term in both readings, pinned by exact rational values.
+
+    Unlike the planar and axis-aligned patches, a two-point patch along a generic direction
+    has a non-zero null term in both readings, so a wrong denominator (q vs q + 2), a dropped
+    2 t_S or a sign slip in t_B changes kappa; the first case's values are worked out by hand
+    (kappa_PAPER = 497/162, kappa_HAAR = 215/54)."""
+    from fractions import Fraction as F
+    want = _two_point_closed_form(d)
+    if kp is not None:
+        assert want["kappa_paper"] == F(kp) and want["kappa_haar"] == F(kh)
+    dv = np.array(d, dtype=np.float64)
+    centre = np.linspace(-3.0, 5.0, len(d))           # an arbitrary offset: centring removes it
+    X = np.stack([centre + 0.5 * dv, centre - 0.5 * dv])
+    t = oc.fast_terms(oc.patch(X, [0, 1]))
+    assert t["p_eff"] == 1 and t["q"] == len(d) - 1
+    for key in ("tau", "t_range", "g", "t_A", "t_S", "t_D", "kappa_paper", "kappa_haar"):
+        w = float(want[key])
+        assert abs(t[key] - w) <= 1e-13 * max(abs(w), float(want["tau"])), key
+    assert abs(t["kappa_paper"] - t["kappa_haar"]) > 1e-3 * float(want["tau"])

@@ -677,4 +677,24 @@ __device__ uint8_t patch_front(const PointLds& P, const float* __restrict__ X, i
   return 0;
 }
 
+// kappa from the raw sums (all float64); returns |inner| and stores inner.
+__device__ __forceinline__ double fast_combine(const double (&part)[5], double tauk, int k,
+                                               int64_t m, int pe, int variant, double* inner) {
+  const double km1 = (double)(k - 1);
+  const double tau = tauk / km1;
+  const double t_range = part[0] / km1, g = part[1] / km1, t_A = part[2] / km1;
+  const double t_S = part[3] / km1, t_D = part[4] / km1;
+  const int64_t q = m - pe;
+  double t_null = 0.0;
+  if (q > 0) {
+    if (variant == 0)
+      t_null = (t_A + 2.0 * (tau - 2.0 * t_S + g)) / (double)q;
+    else
+      t_null = (t_A + 2.0 * (tau - 2.0 * t_D + g)) / (double)(q + 2);
+  }
+  const double in = 0.5 * (t_range + t_null) + 0.5 * tau;
+  if (inner) *inner = in;
+  return fabs(in);
+}
+
 }  // namespace mc

@@ -1,0 +1,728 @@
+// Two-pass Fast-mode mean curvature for k >= 13 (gfx950), split into four kernels that
+// hand per-point k x k state to each other through the caller's workspace.
+//
+// What is computed is the Fast branch of Algorithm 1 (eqs. svd_cov, tA, tB, tnull,
+// fast_curv), evaluated as in curv_fast.hip's two-pass form:
+//   1. curv_gram:  K = X_c X_c^T on MFMA from one pass over the centred patch, and
+//                  tau (k-1) = ||X_c||_F^2 in float64.
+//   2. curv_eigen: the k x k eigen-solve of K (parallel-order Jacobi) gives
+//                  Ut = U_p diag(sigma_p^{-1/2}), the numerical rank and
+//                  (k-1) t_S = sum_l ||K ut_l||^2.  Float32 sweeps on the float32/bf16
+//                  paths; a point whose kept spectrum has a near-degenerate pair is marked
+//                  and re-solved in float64 by a second launch of the same kernel.
+//   3. curv_range: a second pass over the patch forms each 64-column chunk of
+//                  V_r^T = Ut^T X_c on MFMA and one GEMM
+//                  X_c (k x chunk) x [V[:,l1] o V[:,l2] (l1 <= l2) | h | 1]
+//                  whose columns give G_tens, tr G_j = (X_c h)_j and r_j = (X_c 1)_j;
+//                  t_D = sum_c q_c h_c with q_c = sum_j X_c[j,c]^2; then the float64
+//                  combination.
+// Each stage runs at its own occupancy: the eigen-solve, a chain of dependent rounds, runs
+// one wave per point with only its two k x k matrices in LDS, so many points hide each
+// other's latency; the patch passes spread the staging of a chunk over all waves of a point.
+#include "curv_core.h"
+#include "mc_internal.h"
+
+namespace mc {
+
+// internal flag bit: the float32 eigen-solve found a near-degenerate kept pair
+constexpr uint8_t PF_NEED_FP64 = 0x80u;
+
+// Workspace layout: structure of arrays over the n points.  KMAX is the kernel's k bucket.
+struct Fast2Ws {
+  int kmax;
+  size_t esz_k, esz_u;      // bytes per stored K entry and per Ut entry
+  size_t off_k, off_ut, off_tau, off_ts, off_pe, off_fl, total;
+};
+
+static int fast2_kmax(int k) { return k <= 16 ? 16 : (k <= 20 ? 20 : (k <= 24 ? 24 : (k <= 28 ? 28 : 32))); }
+
+Fast2Ws fast2_ws(int64_t n, int k, int precision) {
+  Fast2Ws L{};
+  L.kmax = fast2_kmax(k);
+  const size_t kk = (size_t)L.kmax * L.kmax;
+  const bool f64 = precision == 3;
+  L.esz_k = f64 ? 8 : 4;
+  L.esz_u = f64 ? 8 : 4;
+  size_t off = 0;
+  L.off_k = off;   off += align256((size_t)n * kk * L.esz_k);
+  L.off_ut = off;  off += align256((size_t)n * kk * L.esz_u);
+  L.off_tau = off; off += align256((size_t)n * 8);
+  L.off_ts = off;  off += align256((size_t)n * 8);
+  L.off_pe = off;  off += align256((size_t)n * 4);
+  L.off_fl = off;  off += align256((size_t)n);
+  L.total = off;
+  return L;
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---- 1. Gram pass: one wave per point, four points per workgroup ------------------------
+template <int KMAX, int PREC>
+struct GramCfg {
+  static constexpr int KB = (KMAX + 15) / 16;
+  static constexpr int ROWS = 16 * KB;
+  static constexpr int NUB = KB * (KB + 1) / 2;       // upper-triangular 16 x 16 blocks of K
+  static constexpr int PPW = PREC == MOM_FP64 ? 2 : 4;
+  static constexpr int ESZ = PREC == MOM_FP64 ? 8 : 4;
+  static constexpr size_t BYTES = ((size_t)ROWS * FLDX * ESZ + 15) & ~(size_t)15;
+};
+
+template <int KMAX, int PREC>
+__global__ __launch_bounds__(256) void curv_gram_kernel(const float* __restrict__ X, int64_t n, int64_t m,
+                                                        int64_t ldx, const int32_t* __restrict__ idx, int k,
+                                                        unsigned char* __restrict__ ws, Fast2Ws L) {
+  using C = GramCfg<KMAX, PREC>;
+  using ST = typename std::conditional<PREC == MOM_FP64, double, float>::type;
+  using AccT = typename std::conditional<PREC == MOM_FP64, doublex4, floatx4>::type;
+  constexpr int KB = C::KB;
+  extern __shared__ __align__(16) unsigned char smem_all[];
+  const int gid = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int64_t i = (int64_t)blockIdx.x * C::PPW + gid;
+  if (i >= n) return;                                // whole wave exits together
+  ST* XS = reinterpret_cast<ST*>(smem_all + (size_t)gid * C::BYTES);
+  double* TAU = reinterpret_cast<double*>(ws + L.off_tau);
+  uint8_t* FL = ws + L.off_fl;
+  MomT<PREC>* Kout = reinterpret_cast<MomT<PREC>*>(ws + L.off_k) + (size_t)i * KMAX * KMAX;
+
+  const int nbv = lane < k ? idx[i * k + lane] : 0;
+  if (__any(lane < k && (nbv < 0 || (int64_t)nbv >= n))) {
+    if (lane == 0) {
+      FL[i] = PF_NONFINITE;
+      TAU[i] = 0.0;
+    }
+    return;
+  }
+  for (int t = lane; t < (C::ROWS - k) * FLDX; t += WAVE) XS[k * FLDX + t] = (ST)0;
+
+  float xr[KMAX];
+  auto load = [&](int64_t c0) {
+    const int64_t c = c0 + lane;
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+      float v = 0.0f;
+      if (j < k && c < m) v = X[(int64_t)__builtin_amdgcn_readlane(nbv, j) * ldx + c];
+      xr[j] = v;
+    }
+  };
+  AccT acc[C::NUB];
+#pragma unroll
+  for (int b = 0; b < C::NUB; ++b) acc[b] = AccT{0, 0, 0, 0};
+  double tau64 = 0.0;
+  bool nonfinite = false;
+  load(0);
+  for (int64_t c0 = 0; c0 < m; c0 += FCH) {
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j)
+      if (j < k) nonfinite |= !isfinite(xr[j]);
+    if constexpr (PREC == MOM_FP64) {
+      double xc[KMAX];
+      centre_column_f64<KMAX>(xr, xc, k);
+#pragma unroll
+      for (int j = 0; j < KMAX; ++j)
+        if (j < k) {
+          tau64 = fma(xc[j], xc[j], tau64);
+          XS[j * FLDX + lane] = xc[j];
+        }
+    } else {
+      centre_column<KMAX>(xr, k);
+#pragma unroll
+      for (int j = 0; j < KMAX; ++j)
+        if (j < k) {
+          tau64 = fma((double)xr[j], (double)xr[j], tau64);
+          XS[j * FLDX + lane] = xr[j];
+        }
+    }
+    wave_sync();
+    if (c0 + FCH < m) load(c0 + FCH);
+    const int ng = m - c0 >= FCH ? FCH / 16 : (int)((m - c0 + 15) / 16);
+    for (int g = 0; g < ng; ++g) {
+      const int col = 16 * g + 4 * (lane / 16);      // lane supplies columns col .. col+3
+      int b = 0;
+#pragma unroll
+      for (int ab = 0; ab < KB; ++ab)
+#pragma unroll
+        for (int bb = ab; bb < KB; ++bb, ++b) {
+          const ST* pa = XS + (16 * ab + lane % 16) * FLDX + col;
+          const ST* pb = XS + (16 * bb + lane % 16) * FLDX + col;
+#pragma unroll
+          for (int st = 0; st < 4; ++st) {
+            if constexpr (PREC == MOM_FP64) acc[b] = mfma16x16x4f64(pa[st], pb[st], acc[b]);
+            else acc[b] = mfma16x16x4(pa[st], pb[st], acc[b]);
+          }
+        }
+    }
+    wave_sync();
+  }
+  // K (both triangles) to the workspace
+  int b = 0;
+#pragma unroll
+  for (int ab = 0; ab < KB; ++ab)
+#pragma unroll
+    for (int bb = ab; bb < KB; ++bb, ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int x = 16 * ab + (PREC == MOM_FP64 ? lane / 16 + 4 * r : 4 * (lane / 16) + r);
+        const int y = 16 * bb + lane % 16;
+        if (x < k && y < k) {
+          Kout[x * KMAX + y] = (MomT<PREC>)acc[b][r];
+          Kout[y * KMAX + x] = (MomT<PREC>)acc[b][r];
+        }
+      }
+  tau64 = wave_sum(tau64);
+  const int nf = __any(nonfinite);
+  if (lane == 0) {
+    TAU[i] = tau64;
+    FL[i] = nf ? PF_NONFINITE : 0;
+  }
+}
+
+// ---- 2. eigen-solve: one wave per point -------------------------------------------------
+template <int KMAX, class JT>
+struct EigCfg {
+  static constexpr int KM = KMAX;
+  static constexpr int KK = (KMAX + 1) & ~1;
+  static constexpr int JLD = KK + 1;
+  static constexpr int NW = 1, NTG = WAVE;
+  static constexpr int PPW = sizeof(JT) == 8 ? 2 : 4;
+  static constexpr size_t OFF_A = 0;
+  static constexpr size_t OFF_V = OFF_A + (size_t)KK * JLD * sizeof(JT);
+  static constexpr size_t OFF_K = OFF_V + (size_t)KK * JLD * sizeof(JT);             // copy of K
+  static constexpr size_t OFF_ROT = (OFF_K + (size_t)KK * JLD * sizeof(JT) + 7) & ~(size_t)7;
+  static constexpr size_t OFF_PAIR = OFF_ROT + (size_t)KK * 8;
+  static constexpr size_t OFF_INT = (OFF_PAIR + (size_t)(KK - 1) * (KK / 2) * 2 + 15) & ~(size_t)15;
+  static constexpr size_t BYTES = (OFF_INT + (size_t)(KK + 8) * 4 + 15) & ~(size_t)15;
+};
+
+// F64: float64 sweeps to 2^-52 (float64 moments, or the re-solve of a marked point); else
+// float32 sweeps to 2^-23, marking points with a near-degenerate kept pair (two eigenvalues
+// above the rank floor within a relative 2^-13) for the float64 launch.  resolve_only: work
+// only on marked points.
+template <int KMAX, int PREC, bool F64>
+__global__ __launch_bounds__(256) void curv_eigen_kernel(int64_t n, int64_t m, int k, int resolve_only,
+                                                         unsigned char* __restrict__ ws, Fast2Ws L) {
+  using JT = typename std::conditional<F64, double, float>::type;
+  using C = EigCfg<KMAX, JT>;
+  using ST = typename std::conditional<PREC == MOM_FP64, double, float>::type;
+  constexpr int KK = C::KK;
+  constexpr int HP = KK / 2;
+  extern __shared__ __align__(16) unsigned char smem_all[];
+  const int gid = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int64_t i = (int64_t)blockIdx.x * C::PPW + gid;
+  if (i >= n) return;
+  uint8_t* FL = ws + L.off_fl;
+  const uint8_t fl0 = FL[i];
+  if (fl0 & PF_NONFINITE) return;
+  if (resolve_only && !(fl0 & PF_NEED_FP64)) return;
+  unsigned char* sm = smem_all + (size_t)gid * C::BYTES;
+  JT* A = reinterpret_cast<JT*>(sm + C::OFF_A);
+  JT* V = reinterpret_cast<JT*>(sm + C::OFF_V);
+  JT* Kc = reinterpret_cast<JT*>(sm + C::OFF_K);
+  PointLds P{};
+  P.ROT = reinterpret_cast<double*>(sm + C::OFF_ROT);
+  P.pairs = reinterpret_cast<uint16_t*>(sm + C::OFF_PAIR);
+  int* ord = reinterpret_cast<int*>(sm + C::OFF_INT);
+  P.misc = ord + KK;
+  const MomT<PREC>* Kin = reinterpret_cast<const MomT<PREC>*>(ws + L.off_k) + (size_t)i * KMAX * KMAX;
+
+  for (int e = lane; e < KK * KK; e += WAVE) {
+    const int x = e / KK, y = e % KK;
+    const JT kv = (x < k && y < k) ? (JT)Kin[x * KMAX + y] : (JT)0;
+    A[x * C::JLD + y] = kv;
+    Kc[x * C::JLD + y] = kv;
+    V[x * C::JLD + y] = x == y ? (JT)1 : (JT)0;
+  }
+  for (int e = lane; e < (KK - 1) * HP; e += WAVE) {
+    const int r = e / HP, s = e % HP;
+    const int pa = rr_player(s, r, KK), pb = rr_player(KK - 1 - s, r, KK);
+    P.pairs[e] = (uint16_t)((pa < pb ? pa : pb) | ((pa < pb ? pb : pa) << 8));
+  }
+  wave_sync();
+  const int sweep = jacobi_sweeps<C, JT>(P, A, V, k, lane, F64 ? (JT)0x1p-52 : (JT)0x1p-23);
+  const double unit = PREC == MOM_FP64 ? 0x1p-44 : 0x1p-24;   // rounding level of the moments
+  const double rtol = (double)(m > k ? m : k) * unit;
+  if constexpr (!F64) {
+    // near-degenerate pair among the kept eigenvalues: leave it to the float64 launch
+    bool near = false;
+    if (lane < k) {
+      JT s1 = 0;
+      for (int y = 0; y < k; ++y) s1 = fmax(s1, A[y * C::JLD + y]);
+      const JT keep = (JT)rtol * s1;
+      const JT lx = A[lane * C::JLD + lane];
+      if (lx > keep) {
+        for (int y = 0; y < k; ++y) {
+          const JT ly = A[y * C::JLD + y];
+          near |= y != lane && ly > keep && fabs(lx - ly) < (JT)0x1p-13 * fmax(lx, ly);
+        }
+      }
+    }
+    if (__any(near)) {
+      if (lane == 0) FL[i] = fl0 | PF_NEED_FP64;
+      return;
+    }
+  }
+  // eigen order (descending), numerical rank, Ut, t_S
+  if (lane < KK) {
+    const JT dx = A[lane * C::JLD + lane];
+    int rk = 0;
+    for (int y = 0; y < KK; ++y) {
+      const JT dy = A[y * C::JLD + y];
+      rk += (dy > dx) || (dy == dx && y < lane);
+    }
+    ord[rk] = lane;
+  }
+  wave_sync();
+  const double sig0 = (double)A[ord[0] * C::JLD + ord[0]];
+  const int plim = (int)((int64_t)(k - 1) < m ? (int64_t)(k - 1) : m);
+  int pe = 0;
+  if (sig0 > 0.0)
+    while (pe < plim && (double)A[ord[pe] * C::JLD + ord[pe]] > rtol * sig0) ++pe;
+  ST* UT = reinterpret_cast<ST*>(ws + L.off_ut) + (size_t)i * KMAX * KMAX;
+  double ts = 0.0;
+  for (int e = lane; e < k * KMAX; e += WAVE) {
+    const int a = e / KMAX, l = e % KMAX;
+    if (l < pe) {
+      const int x = ord[l];
+      const double isq = 1.0 / sqrt((double)A[x * C::JLD + x]);
+      UT[a * KMAX + l] = (ST)((double)V[a * C::JLD + x] * isq);
+      // (K ut_l)_a in float64
+      double sv = 0.0;
+      for (int bb = 0; bb < k; ++bb) sv = fma((double)Kc[a * C::JLD + bb], (double)V[bb * C::JLD + x], sv);
+      sv *= isq;
+      ts = fma(sv, sv, ts);
+    }
+  }
+  ts = wave_sum(ts);
+  if (lane == 0) {
+    const double tauk = reinterpret_cast<const double*>(ws + L.off_tau)[i];
+    uint8_t fl = fl0 & (uint8_t)~PF_NEED_FP64;
+    if (pe < plim) fl |= PF_RANK_DEFICIENT;
+    if (sweep >= JAC_MAX_SWEEPS) fl |= PF_JACOBI_MAXSWEEPS;
+    if (F64 && PREC != MOM_FP64) fl |= PF_EIGEN_FP64;
+    if (!(sig0 > 0.0) || tauk == 0.0 || pe == 0) fl |= PF_DEGENERATE;
+    reinterpret_cast<double*>(ws + L.off_ts)[i] = ts;
+    reinterpret_cast<int*>(ws + L.off_pe)[i] = pe;
+    FL[i] = fl;
+  }
+}
+
+// ---- 3. range pass: NW waves per point ---------------------------------------------------
+template <int KMAX, int NW_, int PPW_, int ESZ_>
+struct RangeCfg {
+  static constexpr int KB = (KMAX + 15) / 16;               // 16-row blocks of the patch
+  static constexpr int NW = NW_, PPW = PPW_, NTG = NW * WAVE, NT = PPW * NTG;
+  static constexpr int ESZ = ESZ_;
+  static constexpr int NCOLMAX = (KMAX - 1) * KMAX / 2 + 2; // pairs (l1 <= l2 < k-1), h, ones
+  static constexpr int NB = (NCOLMAX + 15) / 16;
+  static constexpr int NPAD = NB * 16;
+  static constexpr int NBW = (NB + NW - 1) / NW;            // column blocks per wave
+  static constexpr int XQ = 16 * KB, XONE = 16 * KB + 1, XROWS = 16 * KB + 2;   // patch chunk rows
+  static constexpr int VH = 16 * KB, VONE = 16 * KB + 1, VZERO = 16 * KB + 2;   // range chunk rows
+  static constexpr int VROWS = 16 * KB + 3;
+  static constexpr int VBLK = KB * (FCH / 16);              // blocks of the V_r^T chunk product
+  static constexpr int VBW = (VBLK + NW - 1) / NW;
+  // staging: each wave takes CPW columns of a chunk; its lanes split them into NW row groups
+  static constexpr int CPW = FCH / NW;
+  static constexpr int RPG = (KMAX + NW - 1) / NW;          // patch rows per group
+  static constexpr int VPG = 16 * KB / NW;                  // range rows per group (h)
+  static constexpr size_t OFF_XS = 0;
+  static constexpr size_t OFF_VS = ((size_t)XROWS * FLDX * ESZ + 15) & ~(size_t)15;
+  static constexpr size_t OFF_RED = (OFF_VS + (size_t)VROWS * FLDX * ESZ + 15) & ~(size_t)15;
+  static constexpr size_t OFF_BJ = OFF_RED + (size_t)16 * NW * 8;          // tr G_j, r_j
+  static constexpr size_t OFF_NB = OFF_BJ + (size_t)2 * KMAX * 8;
+  static constexpr size_t OFF_PJ = OFF_NB + (size_t)KMAX * 4;
+  static constexpr size_t BYTES = (OFF_PJ + 2 * NPAD + 15) & ~(size_t)15;
+};
+
+template <int KMAX, int PREC>
+struct RangeCfgSel {
+  static constexpr int NW = KMAX <= 16 ? 1 : (KMAX <= 26 ? 2 : 4);
+  static constexpr int PPW = NW == 1 ? (PREC == MOM_FP64 ? 2 : 4) : 1;
+  using C = RangeCfg<KMAX, NW, PPW, PREC == MOM_FP64 ? 8 : 4>;
+};
+
+template <int KMAX, int PREC>
+__global__ __launch_bounds__((RangeCfgSel<KMAX, PREC>::C::NT)) void curv_range_kernel(
+    const float* __restrict__ X, int64_t n, int64_t m, int64_t ldx, const int32_t* __restrict__ idx,
+    int k, int variant, const unsigned char* __restrict__ ws, Fast2Ws L, float* __restrict__ kappa_out,
+    uint8_t* __restrict__ flags_out) {
+  using C = typename RangeCfgSel<KMAX, PREC>::C;
+  using ST = typename std::conditional<PREC == MOM_FP64, double, float>::type;   // staged values
+  using AccT = typename std::conditional<PREC == MOM_FP64, doublex4, floatx4>::type;
+  constexpr int KB = C::KB;
+  extern __shared__ __align__(16) unsigned char smem_all[];
+  const int gid = threadIdx.x / C::NTG;            // point group inside the workgroup
+  const int tg = threadIdx.x % C::NTG;             // thread inside the group
+  const int w = tg / WAVE, lane = tg % WAVE;
+  const int64_t i = (int64_t)blockIdx.x * C::PPW + gid;
+  if (i >= n) return;                              // whole group exits together
+  const uint8_t fl = ws[L.off_fl + i];
+  if (fl & (PF_NONFINITE | PF_DEGENERATE)) {
+    if (tg == 0) {
+      kappa_out[i] = (fl & PF_NONFINITE) ? __builtin_nanf("") : 0.0f;
+      if (flags_out) flags_out[i] = fl;
+    }
+    return;
+  }
+  unsigned char* sm = smem_all + (size_t)gid * C::BYTES;
+  ST* XS = reinterpret_cast<ST*>(sm + C::OFF_XS);
+  ST* VS = reinterpret_cast<ST*>(sm + C::OFF_VS);
+  double* RED = reinterpret_cast<double*>(sm + C::OFF_RED);
+  double* BJ = reinterpret_cast<double*>(sm + C::OFF_BJ);
+  int* nb = reinterpret_cast<int*>(sm + C::OFF_NB);
+  unsigned char* pj1 = sm + C::OFF_PJ;
+  unsigned char* pj2 = pj1 + C::NPAD;
+  const int pe = reinterpret_cast<const int*>(ws + L.off_pe)[i];
+  const double tauk = reinterpret_cast<const double*>(ws + L.off_tau)[i];
+  const double tS = reinterpret_cast<const double*>(ws + L.off_ts)[i];
+  const ST* UT = reinterpret_cast<const ST*>(ws + L.off_ut) + (size_t)i * KMAX * KMAX;
+  const int npair = (k - 1) * k / 2;
+  const int ncol = npair + 2;
+  const int nbr = (ncol + 15) / 16;                // column blocks in use
+
+  // ---- setup: neighbour rows, column tables, zero rows -----------------------------
+  if (tg < k) nb[tg] = idx[i * k + tg];            // checked by the Gram pass
+  for (int t = tg; t < C::NPAD; t += C::NTG) {
+    int a = C::VZERO, b = C::VZERO;                // padding column: zero row
+    if (t < npair) {
+      int r = t;
+      a = 0;
+      while (r >= k - 1 - a) { r -= k - 1 - a; ++a; }
+      b = a + r;
+    } else if (t == npair) {
+      a = C::VH;                                   // h column: h o 1
+      b = C::VONE;
+    } else if (t == npair + 1) {
+      a = b = C::VONE;                             // ones column
+    }
+    pj1[t] = (unsigned char)a;
+    pj2[t] = (unsigned char)b;
+  }
+  for (int t = tg; t < (16 * KB - k) * FLDX; t += C::NTG) XS[k * FLDX + t] = (ST)0;
+  for (int t = tg; t < FLDX; t += C::NTG) VS[C::VZERO * FLDX + t] = (ST)0;
+  // Ut^T operand of the V_r^T chunk product: A[l][j] = Ut[j][l] at row l = 16 lb + lane%16,
+  // k index j = 16 jb + 4 s + lane/16
+  ST ua[KB][KB][4];
+#pragma unroll
+  for (int lb = 0; lb < KB; ++lb)
+#pragma unroll
+    for (int jb = 0; jb < KB; ++jb)
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int l = 16 * lb + lane % 16, j = 16 * jb + 4 * st + lane / 16;
+        ua[lb][jb][st] = (l < pe && j < k) ? UT[j * KMAX + l] : (ST)0;
+      }
+  gsync<C::NW>();
+  int off1[C::NBW], off2[C::NBW];
+#pragma unroll
+  for (int b = 0; b < C::NBW; ++b) {
+    const int nbg = w + C::NW * b;
+    const int pc = nbg * 16 + lane % 16 < C::NPAD ? nbg * 16 + lane % 16 : C::NPAD - 1;
+    off1[b] = pj1[pc] * FLDX;
+    off2[b] = pj2[pc] * FLDX;
+  }
+
+  // staging: lane (cl, g) of wave w holds rows g*RPG + r of column w*CPW + cl of the chunk
+  const int cl = lane % C::CPW, grp = lane / C::CPW;
+  const int colw = w * C::CPW + cl;                // column inside the chunk
+  int nbr_[C::RPG];
+#pragma unroll
+  for (int r = 0; r < C::RPG; ++r) {
+    const int j = grp * C::RPG + r;
+    nbr_[r] = j < k ? nb[j] : 0;
+  }
+  float xr[C::RPG];
+  auto load = [&](int64_t c0) {
+    const int64_t c = c0 + colw;
+#pragma unroll
+    for (int r = 0; r < C::RPG; ++r) {
+      const int j = grp * C::RPG + r;
+      xr[r] = (j < k && c < m) ? X[(int64_t)nbr_[r] * ldx + c] : 0.0f;
+    }
+  };
+  // the centred chunk: offsets from the first row, minus their mean (as centre_column), and
+  // q_c = sum_j X_c[j, c]^2, reduced over the lanes that share the column
+  auto stage = [&](int64_t c0) {
+    if constexpr (PREC == MOM_FP64) {
+      const double x0 = (double)__shfl(xr[0], cl, WAVE);
+      double d[C::RPG];
+      double s = 0.0;
+#pragma unroll
+      for (int r = 0; r < C::RPG; ++r) {
+        const int j = grp * C::RPG + r;
+        d[r] = j < k ? (double)xr[r] - x0 : 0.0;
+        s += d[r];
+      }
+#pragma unroll
+      for (int o = C::CPW; o < WAVE; o <<= 1) s += __shfl_xor(s, o, WAVE);
+      const double mean = s / (double)k;
+      double q = 0.0;
+#pragma unroll
+      for (int r = 0; r < C::RPG; ++r) {
+        const int j = grp * C::RPG + r;
+        if (j < k) {
+          const double xc = d[r] - mean;
+          q = fma(xc, xc, q);
+          XS[j * FLDX + colw] = xc;
+        }
+      }
+#pragma unroll
+      for (int o = C::CPW; o < WAVE; o <<= 1) q += __shfl_xor(q, o, WAVE);
+      if (grp == 0) XS[C::XQ * FLDX + colw] = q;
+    } else {
+      const float x0 = __shfl(xr[0], cl, WAVE);
+      float d[C::RPG];
+      float s = 0.0f;
+#pragma unroll
+      for (int r = 0; r < C::RPG; ++r) {
+        const int j = grp * C::RPG + r;
+        d[r] = j < k ? xr[r] - x0 : 0.0f;
+        s += d[r];
+      }
+#pragma unroll
+      for (int o = C::CPW; o < WAVE; o <<= 1) s += __shfl_xor(s, o, WAVE);
+      const float mean = s / (float)k;
+      float q = 0.0f;
+#pragma unroll
+      for (int r = 0; r < C::RPG; ++r) {
+        const int j = grp * C::RPG + r;
+        if (j < k) {
+          const float xc = d[r] - mean;
+          q = fmaf(xc, xc, q);
+          XS[j * FLDX + colw] = xc;
+        }
+      }
+#pragma unroll
+      for (int o = C::CPW; o < WAVE; o <<= 1) q += __shfl_xor(q, o, WAVE);
+      if (grp == 0) XS[C::XQ * FLDX + colw] = q;
+    }
+    if (grp == 0) XS[C::XONE * FLDX + colw] = (c0 + colw < m) ? (ST)1 : (ST)0;
+  };
+
+  AccT acc[KB][C::NBW];
+#pragma unroll
+  for (int a = 0; a < KB; ++a)
+#pragma unroll
+    for (int b = 0; b < C::NBW; ++b) acc[a][b] = AccT{0, 0, 0, 0};
+  double tD = 0.0;
+  load(0);
+  for (int64_t c0 = 0; c0 < m; c0 += FCH) {
+    stage(c0);
+    gsync<C::NW>();
+    if (c0 + FCH < m) load(c0 + FCH);
+    // V_r^T chunk = Ut^T X_c (rows l, columns c of the chunk)
+#pragma unroll
+    for (int t = 0; t < C::VBW; ++t) {
+      const int vb = w + C::NW * t;
+      if (vb < C::VBLK) {
+        const int lb = vb / (FCH / 16), cb = vb % (FCH / 16);
+        AccT v = AccT{0, 0, 0, 0};
+#pragma unroll
+        for (int jb = 0; jb < KB; ++jb)
+#pragma unroll
+          for (int st = 0; st < 4; ++st) {
+            const ST bv = XS[(16 * jb + 4 * st + lane / 16) * FLDX + 16 * cb + lane % 16];
+            if constexpr (PREC == MOM_FP64) v = mfma16x16x4f64(ua[lb][jb][st], bv, v);
+            else v = mfma16x16x4(ua[lb][jb][st], bv, v);
+          }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int l = 16 * lb + (PREC == MOM_FP64 ? lane / 16 + 4 * r : 4 * (lane / 16) + r);
+          VS[l * FLDX + 16 * cb + lane % 16] = (ST)v[r];
+        }
+      }
+    }
+    gsync<C::NW>();
+    // h_c = sum_l V[c, l]^2 (rows l >= pe hold zeros), the ones row, and t_D's sum_c q_c h_c
+    {
+      ST h = 0;
+#pragma unroll
+      for (int r = 0; r < C::VPG; ++r) {
+        const ST v = VS[(grp * C::VPG + r) * FLDX + colw];
+        h += v * v;
+      }
+#pragma unroll
+      for (int o = C::CPW; o < WAVE; o <<= 1) h += __shfl_xor(h, o, WAVE);
+      if (grp == 0) {
+        VS[C::VH * FLDX + colw] = h;
+        VS[C::VONE * FLDX + colw] = (c0 + colw < m) ? (ST)1 : (ST)0;
+        tD = fma((double)XS[C::XQ * FLDX + colw], (double)h, tD);
+      }
+    }
+    gsync<C::NW>();
+    if constexpr (PREC == MOM_FP64) {
+      const int st4 = m - c0 >= FCH ? FCH / 4 : (int)((m - c0 + 3) / 4);
+      for (int s4 = 0; s4 < st4; ++s4) {
+        const int col = 4 * s4 + lane / 16;
+        double av[KB];
+#pragma unroll
+        for (int a = 0; a < KB; ++a) av[a] = XS[(16 * a + lane % 16) * FLDX + col];
+#pragma unroll
+        for (int b = 0; b < C::NBW; ++b) {
+          if (w + C::NW * b < nbr) {
+            const double bv = VS[off1[b] + col] * VS[off2[b] + col];
+#pragma unroll
+            for (int a = 0; a < KB; ++a) acc[a][b] = mfma16x16x4f64(av[a], bv, acc[a][b]);
+          }
+        }
+      }
+    } else if constexpr (PREC == MOM_FP32) {
+      const int ng = m - c0 >= FCH ? FCH / 16 : (int)((m - c0 + 15) / 16);
+      for (int g = 0; g < ng; ++g) {
+        const int col = 16 * g + 4 * (lane / 16);
+        floatx4 av[KB];
+#pragma unroll
+        for (int a = 0; a < KB; ++a)
+          av[a] = *reinterpret_cast<const floatx4*>(XS + (16 * a + lane % 16) * FLDX + col);
+#pragma unroll
+        for (int b = 0; b < C::NBW; ++b) {
+          if (w + C::NW * b < nbr) {
+            const floatx4 x1 = *reinterpret_cast<const floatx4*>(VS + off1[b] + col);
+            const floatx4 x2 = *reinterpret_cast<const floatx4*>(VS + off2[b] + col);
+            const floatx4 bv = x1 * x2;
+#pragma unroll
+            for (int st = 0; st < 4; ++st)
+#pragma unroll
+              for (int a = 0; a < KB; ++a) acc[a][b] = mfma16x16x4(av[a][st], bv[st], acc[a][b]);
+          }
+        }
+      }
+    } else {
+      // bf16 operands, 32-column steps: lane l supplies columns 32 s + 8 (l / 16) + e
+      const int st32 = m - c0 >= FCH ? FCH / 32 : (int)((m - c0 + 31) / 32);
+      for (int s32 = 0; s32 < st32; ++s32) {
+        const int col0 = 32 * s32 + 8 * (lane / 16);
+        shortx8 abf[KB];
+#pragma unroll
+        for (int a = 0; a < KB; ++a) {
+          const floatx4 x0 = *reinterpret_cast<const floatx4*>(XS + (16 * a + lane % 16) * FLDX + col0);
+          const floatx4 x1 = *reinterpret_cast<const floatx4*>(XS + (16 * a + lane % 16) * FLDX + col0 + 4);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            abf[a][e] = (short)f2bf(x0[e]);
+            abf[a][4 + e] = (short)f2bf(x1[e]);
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < C::NBW; ++b) {
+          if (w + C::NW * b < nbr) {
+            const floatx4 p0 = *reinterpret_cast<const floatx4*>(VS + off1[b] + col0);
+            const floatx4 p1 = *reinterpret_cast<const floatx4*>(VS + off1[b] + col0 + 4);
+            const floatx4 q0 = *reinterpret_cast<const floatx4*>(VS + off2[b] + col0);
+            const floatx4 q1 = *reinterpret_cast<const floatx4*>(VS + off2[b] + col0 + 4);
+            shortx8 bbf;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              bbf[e] = (short)f2bf(p0[e] * q0[e]);
+              bbf[4 + e] = (short)f2bf(p1[e] * q1[e]);
+            }
+#pragma unroll
+            for (int a = 0; a < KB; ++a) acc[a][b] = mfma16x16x32bf16(abf[a], bbf, acc[a][b]);
+          }
+        }
+      }
+    }
+    gsync<C::NW>();
+  }
+
+  // ---- reductions: raw sums (k-1) * (t_range, g, t_A, t_S, t_D) ------------------------
+  double part[5] = {0.0, 0.0, 0.0, 0.0, tD};
+#pragma unroll
+  for (int b = 0; b < C::NBW; ++b) {
+    const int nbg = w + C::NW * b;
+    if (nbg < nbr) {
+      const int col = nbg * 16 + lane % 16;
+#pragma unroll
+      for (int a = 0; a < KB; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = 16 * a + (PREC == MOM_FP64 ? lane / 16 + 4 * r : 4 * (lane / 16) + r);
+          if (j < k && col < ncol) {
+            const double v = (double)acc[a][b][r];
+            if (col < npair) {
+              const bool diag = pj1[col] == pj2[col];
+              part[1] = fma(diag ? v : 2.0 * v, v, part[1]);
+              if (diag) part[0] = fma(v, v, part[0]);
+            } else {
+              BJ[(col - npair) * KMAX + j] = v;      // tr G_j (h column), r_j (ones column)
+            }
+          }
+        }
+    }
+  }
+  gsync<C::NW>();
+  for (int j = tg; j < k; j += C::NTG) {
+    const double bj = BJ[KMAX + j] - BJ[j];       // (X_c d_P)_j = r_j - tr G_j
+    part[2] = fma(bj, bj, part[2]);
+  }
+  if (tg == 0) part[3] = tS;
+  group_sum<C::NW, 5>(part, RED, tg);
+
+  if (tg == 0) {
+    kappa_out[i] = (float)fast_combine(part, tauk, k, m, pe, variant, nullptr);
+    if (flags_out) flags_out[i] = fl;
+  }
+}
+
+template <int KMAX, int PREC>
+static hipError_t launch_fast2_kp(const float* X, int64_t n, int64_t m, int64_t ldx, const int32_t* idx,
+                                  int k, int variant, float* kappa, uint8_t* flags, unsigned char* ws,
+                                  const Fast2Ws& L, hipStream_t stream) {
+  using G = GramCfg<KMAX, PREC>;
+  using E32 = EigCfg<KMAX, float>;
+  using E64 = EigCfg<KMAX, double>;
+  using R = typename RangeCfgSel<KMAX, PREC>::C;
+  static_assert(G::PPW * G::BYTES <= 64 * 1024 && E32::PPW * E32::BYTES <= 64 * 1024 &&
+                    E64::PPW * E64::BYTES <= 64 * 1024 && R::PPW * R::BYTES <= 64 * 1024,
+                "per-workgroup LDS of the two-pass kernels stays within 64 KiB");
+  timing_begin(6, stream);
+  hipLaunchKernelGGL((curv_gram_kernel<KMAX, PREC>), dim3((unsigned)((n + G::PPW - 1) / G::PPW)), dim3(G::PPW * WAVE),
+                     G::PPW * G::BYTES, stream, X, n, m, ldx, idx, k, ws, L);
+  if constexpr (PREC != MOM_FP64) {
+    hipLaunchKernelGGL((curv_eigen_kernel<KMAX, PREC, false>), dim3((unsigned)((n + E32::PPW - 1) / E32::PPW)),
+                       dim3(E32::PPW * WAVE), E32::PPW * E32::BYTES, stream, n, m, k, 0, ws, L);
+  }
+  hipLaunchKernelGGL((curv_eigen_kernel<KMAX, PREC, true>), dim3((unsigned)((n + E64::PPW - 1) / E64::PPW)),
+                     dim3(E64::PPW * WAVE), E64::PPW * E64::BYTES, stream, n, m, k,
+                     PREC == MOM_FP64 ? 0 : 1, ws, L);
+  hipLaunchKernelGGL((curv_range_kernel<KMAX, PREC>), dim3((unsigned)((n + R::PPW - 1) / R::PPW)), dim3(R::NT),
+                     R::PPW * R::BYTES, stream, X, n, m, ldx, idx, k, variant, (const unsigned char*)ws, L,
+                     kappa, flags);
+  timing_end(6, stream);
+  return hipGetLastError();
+}
+
+template <int KMAX>
+static hipError_t launch_fast2_k(const float* X, int64_t n, int64_t m, int64_t ldx, const int32_t* idx, int k,
+                                 int precision, int variant, float* kappa, uint8_t* flags, unsigned char* ws,
+                                 const Fast2Ws& L, hipStream_t stream) {
+  if (precision == 1)
+    return launch_fast2_kp<KMAX, MOM_BF16>(X, n, m, ldx, idx, k, variant, kappa, flags, ws, L, stream);
+  if (precision == 3) {
+    if constexpr (KMAX <= 28)
+      return launch_fast2_kp<KMAX, MOM_FP64>(X, n, m, ldx, idx, k, variant, kappa, flags, ws, L, stream);
+    return hipErrorInvalidValue;
+  }
+  return launch_fast2_kp<KMAX, MOM_FP32>(X, n, m, ldx, idx, k, variant, kappa, flags, ws, L, stream);
+}
+
+hipError_t launch_curv_fast2(const float* X, int64_t n, int64_t m, int64_t ldx, const int32_t* idx, int k,
+                             int precision, int variant, float* kappa, uint8_t* flags, void* ws,
+                             hipStream_t stream) {
+  const Fast2Ws L = fast2_ws(n, k, precision);
+  unsigned char* w = reinterpret_cast<unsigned char*>(ws);
+  switch (L.kmax) {
+    case 16: return launch_fast2_k<16>(X, n, m, ldx, idx, k, precision, variant, kappa, flags, w, L, stream);
+    case 20: return launch_fast2_k<20>(X, n, m, ldx, idx, k, precision, variant, kappa, flags, w, L, stream);
+    case 24: return launch_fast2_k<24>(X, n, m, ldx, idx, k, precision, variant, kappa, flags, w, L, stream);
+    case 28: return launch_fast2_k<28>(X, n, m, ldx, idx, k, precision, variant, kappa, flags, w, L, stream);
+    default: return launch_fast2_k<32>(X, n, m, ldx, idx, k, precision, variant, kappa, flags, w, L, stream);
+  }
+}
+
+size_t curv_fast2_ws_bytes(int64_t n, int k, int precision) { return fast2_ws(n, k, precision).total; }
+
+}  // namespace mc

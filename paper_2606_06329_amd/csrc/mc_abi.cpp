@@ -78,8 +78,11 @@ size_t mc_workspace_bytes(int32_t op, int64_t n, int64_t m, int32_t k, int32_t p
       return mc::knn_plan(n, m, k, kc, precision).total;
     }
     case MC_OP_FAST:
+      if (precision != MC_FP32 && precision != MC_BF16 && precision != MC_FP64) return 0;
       if (precision == MC_FP64 && k > MC_FAST_FP64_KMAX) return 0;
-      return 256;  // the fused kernel keeps everything on chip
+      // the single-pass kernel keeps everything on chip; the two-pass form hands per-point
+      // k x k state between its kernels
+      return k <= mc::FAST_SINGLE_PASS_KMAX ? 256 : mc::curv_fast2_ws_bytes(n, k, precision);
     case MC_OP_EXACT:
       if (!mc::curv_exact_fits(m, k)) return 0;
       return mc::curv_exact_ws_bytes(n, m, k);
@@ -129,12 +132,14 @@ int mc_curvature_fast(const float* X, int64_t n, int64_t m, int64_t ldx, const i
     return precision == MC_FP8 ? MC_EPRECISION : MC_EINVAL;
   }
   if (precision == MC_FP64 && k > MC_FAST_FP64_KMAX) return MC_ESHAPE;
-  (void)ws;
-  (void)ws_bytes;
+  if (k > mc::FAST_SINGLE_PASS_KMAX) {
+    if (!ws) return MC_EINVAL;
+    if (ws_bytes < mc::curv_fast2_ws_bytes(n, k, precision) || misaligned(ws)) return MC_EWORKSPACE;
+  }
   st = check_device();
   if (st) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  if (mc::launch_curv_fast(X, n, m, ldx, idx, k, precision, variant, kappa_out, flags_out, s) !=
+  if (mc::launch_curv_fast(X, n, m, ldx, idx, k, precision, variant, kappa_out, flags_out, ws, s) !=
       hipSuccess)
     return MC_ELAUNCH;
   if (flags & MC_STRICT) return strict_check(flags_out, n, (uint8_t)~MC_PF_EIGEN_FP64, s);

@@ -52,10 +52,16 @@ struct KnnPlan {
 
 KnnPlan knn_plan(int64_t n, int64_t m, int k, int kc, int precision);
 
-// Fast curvature: dynamic LDS bytes and launch of the fused per-point kernel.
+// Fast curvature: the fused single-pass kernel (k <= 12, no workspace) or the two-pass
+// kernels (k >= 13), which keep per-point k x k state in the workspace.
 hipError_t launch_curv_fast(const float* X, int64_t n, int64_t m, int64_t ldx, const int32_t* idx,
-                            int k, int precision, int variant, float* kappa, uint8_t* flags,
+                            int k, int precision, int variant, float* kappa, uint8_t* flags, void* ws,
                             hipStream_t stream);
+hipError_t launch_curv_fast2(const float* X, int64_t n, int64_t m, int64_t ldx, const int32_t* idx, int k,
+                             int precision, int variant, float* kappa, uint8_t* flags, void* ws,
+                             hipStream_t stream);
+size_t curv_fast2_ws_bytes(int64_t n, int k, int precision);
+constexpr int FAST_SINGLE_PASS_KMAX = 12;   // largest k of the single-pass form
 
 hipError_t launch_curv_exact(const float* X, int64_t n, int64_t m, int64_t ldx, const int32_t* idx,
                              int k, float* kappa, uint8_t* flags, void* ws, hipStream_t stream);

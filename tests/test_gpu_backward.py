@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 from oracle import adjoint as oa
+from oracle import curvature as oc
 from oracle import knn as ok
 from paper_2606_06329_amd import synth
 from tests.gpu_common import to_dev
@@ -95,35 +96,64 @@ def test_backward_swissroll_full_size():
     euler = float(np.sum(X.astype(np.float64) * g))
     assert abs(euler - 2 * L) <= 1e-3 * np.sum(np.abs(X * g))
     # central differences of the GPU forward (float64 moments, float32 output) with the lists
-    # fixed.  Only the patches that contain point i change (the others see bit-identical
-    # inputs), so the rounding floor of the difference quotient is that of those patches'
-    # float32 outputs: an ulp of sum |w_j| kappa_j over them (0.5 ulp each side), over 2h.
+    # fixed, at h and 2h.  Only the patches that contain point i change (the others see
+    # bit-identical inputs), so the rounding floor of a difference quotient is that of those
+    # patches' float32 outputs: an ulp of sum |w_j| kappa_j over them, over 2h.  The swiss
+    # roll's patches have nine noise directions of nearly equal variance, where t_range turns
+    # sharply, so the truncation error of the h = 1e-3 quotient is estimated from the 2h one
+    # (Richardson) and the comparison uses the extrapolated value, within that estimate.
     rng = np.random.default_rng(7)
     idx_np = idx.cpu().numpy()
     kap_np = kap.cpu().numpy().astype(np.float64)
     deg = np.bincount(idx_np.ravel(), minlength=n)
     cand = np.nonzero(deg > 0)[0]
     h = 1e-3
+
+    def quotient(i, a, hh):
+        Xp = Xd.clone(); Xp[i, a] += hh
+        Xm = Xd.clone(); Xm[i, a] -= hh
+        kp, _ = P.curvature_fast(Xp, idx, "paper", "fp64")
+        km, _ = P.curvature_fast(Xm, idx, "paper", "fp64")
+        return float((wd.double() * (kp.double() - km.double())).sum()) / (2 * hh)
+
+    X64 = X.astype(np.float64)
     bad = 0
-    checked_rel = 0                  # coordinates where the bound is tighter than 5 %
+    kinks = 0                        # the secant over [-h, h] crosses a sharp turn of t_range
+    tight = 0                        # coordinates where the bound is tighter than 5 %
     for t in range(64):
         i = int(rng.choice(cand))
         a = int(rng.integers(0, m))
-        Xp = Xd.clone(); Xp[i, a] += h
-        Xm = Xd.clone(); Xm[i, a] -= h
-        kp, _ = P.curvature_fast(Xp, idx, "paper", "fp64")
-        km, _ = P.curvature_fast(Xm, idx, "paper", "fp64")
-        fd = float((wd.double() * (kp.double() - km.double())).sum()) / (2 * h)
+        f1, f2 = quotient(i, a, h), quotient(i, a, 2 * h)
+        fdr = f1 + (f1 - f2) / 3.0
         owners = np.nonzero((idx_np == i).any(1))[0]
         floor = 2 * 2.0 ** -24 * float(np.sum(np.abs(w[owners]) * kap_np[owners])) / (2 * h)
-        tol = max(1e-3 * abs(g[i, a]), floor)
-        checked_rel += tol < 0.05 * abs(g[i, a])
-        if abs(fd - g[i, a]) > tol:
-            bad += 1
-            print("fd mismatch", i, a, fd, g[i, a], tol)
-    print(f"  FD: {checked_rel} of 64 coordinates checked to better than 5 % relative", flush=True)
+        tol = max(1e-3 * abs(g[i, a]), 2 * floor, 0.5 * abs(f1 - f2))
+        tight += tol < 0.05 * abs(g[i, a])
+        if abs(fdr - g[i, a]) <= tol:
+            continue
+        # A mismatch is accepted only when the float64 oracle shows that it belongs to the
+        # function, not to the kernels: its own difference quotient over the same [-h, h]
+        # reproduces the GPU's, and its exact derivative at X equals the GPU gradient.
+        sub_w = w[owners].astype(np.float64)
+        _, g_or = oa.loss_and_grad(X64, idx_np[owners], sub_w, "paper")
+        Lo = []
+        for sgn in (1.0, -1.0):
+            Xs = X64.copy()
+            Xs[i, a] += sgn * h
+            Lo.append(sum(sub_w[r] * oc.fast_kappa(oc.patch(Xs, idx_np[o]), "paper")
+                          for r, o in enumerate(owners)))
+        fd_or = (Lo[0] - Lo[1]) / (2 * h)
+        explained = (abs(fd_or - f1) <= 1e-3 * abs(f1) + 4 * floor and
+                     abs(g_or[i, a] - g[i, a]) <= 1e-4 * abs(g_or[i, a]) + 1e-9)
+        print("fd mismatch", i, a, f1, f2, fdr, g[i, a], tol, "oracle fd", fd_or, "oracle grad",
+              g_or[i, a], "explained" if explained else "UNEXPLAINED")
+        kinks += explained
+        bad += not explained
+    print(f"  FD: {tight} of 64 coordinates checked to better than 5 % relative; "
+          f"{kinks} secants across a sharp turn, confirmed by the oracle", flush=True)
     assert bad == 0
-    assert checked_rel >= 32
+    assert kinks <= 4
+    assert tight >= 32
     # float64 oracle on a sub-loss over 150 random points (exact gradient of that sub-loss)
     sel = rng.choice(n, 150, replace=False)
     ws = np.zeros(n, np.float32)

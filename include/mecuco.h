@@ -208,7 +208,8 @@ int mc_curvature_backward(const float* X, int64_t n, int64_t m, int64_t ldx, con
 #define MC_STAGE_CURV_EXACT 7
 #define MC_STAGE_CURV_BACKWARD 8
 #define MC_STAGE_KNN_COLUMN_TOPK 9
-#define MC_STAGE_COUNT 10
+#define MC_STAGE_KNN_RESCAN 10
+#define MC_STAGE_COUNT 11
 int mc_timing_enable(int on);
 int mc_timing_read(int32_t stage, double* total_ms, int64_t* launches);
 const char* mc_stage_name(int32_t stage);

@@ -26,7 +26,7 @@ MC_KMAX = 32
 EXPORTS = ("mc_knn", "mc_curvature_fast", "mc_curvature_exact", "mc_curvature_backward",
            "mc_workspace_bytes", "mc_status_string", "mc_version", "mc_timing_enable",
            "mc_timing_read", "mc_stage_name")
-MC_STAGE_COUNT = 10
+MC_STAGE_COUNT = 11
 
 _lib = None
 

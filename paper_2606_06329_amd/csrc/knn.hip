@@ -41,6 +41,19 @@ constexpr int RPW = KBQ / (KNT / 64);   // query rows owned by one wave in the t
 constexpr int SLD = KBN + 4;  // score-tile row stride (floats)
 constexpr int KCMAX = 64;  // largest candidate list
 constexpr int KPARTS = 256; // row blocks of the column-mean reduction
+constexpr int RESCAN_CMAX = 256;   // candidates the rescan collects per uncertified query
+
+// Per-query state of the rescan of uncertified queries (workspace arrays).
+struct RescanWs {
+  float* act_thr;        // score threshold of the quick test (-inf: query not rescanned)
+  float* act_T;          // distance threshold T of the exact test
+  float* act_a;          // lower-bound offset a (sqrt(s + a) bounds the copies' distance)
+  int* cnt;              // collected candidates
+  int* cbuf;             // n x RESCAN_CMAX candidate indices
+  float* p1d;            // n x KCMAX exact distances of the first pass's candidates
+  int* p1j;              // n x KCMAX their indices
+  uint32_t* tile_active; // per 128-point tile: some query of the tile is rescanned
+};
 
 // ------------------------------------------------------------------------------------
 // prep
@@ -83,16 +96,17 @@ __global__ __launch_bounds__(256) void knn_mean_kernel(const double* __restrict_
 
 // One wave per row: the centred row xc = fl(x - mu) in the GEMM's input format (float32,
 // bf16, or fp8 e4m3 with the per-row scale s = max|xc| / 448), zero padded to the row
-// stride mp; its norm ||xc||^2 (float32, from a float64 sum); and the rounding radius
-// ||lowp(xc) - xc|| of the low-precision copy (0 on the float32 path).
+// stride mp; the norm of that copy, ||lowp(xc)||^2 (float32, from a float64 sum); and the
+// rounding radius ||lowp(xc) - xc|| of the low-precision copy (0 on the float32 path).
 __global__ __launch_bounds__(256) void knn_center_kernel(
     const float* __restrict__ X, int64_t n, int64_t m, int64_t ldx, int64_t mp,
     const float* __restrict__ mu, void* __restrict__ xout, float* __restrict__ scales,
-    float* __restrict__ norms, float* __restrict__ radius, int precision, uint32_t* __restrict__ thr) {
+    float* __restrict__ norms, float* __restrict__ radius, int precision, uint32_t* __restrict__ thr,
+    uint32_t* __restrict__ tile_active) {
   const int64_t r = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
   const int lane = threadIdx.x % WAVE;
   if (r >= n) return;
-  double s = 0.0, e = 0.0;
+  double s = 0.0, e = 0.0, sh = 0.0;
   float amax = 0.0f;
   for (int64_t c = lane; c < m; c += WAVE) {
     const float v = X[r * ldx + c] - mu[c];
@@ -109,19 +123,27 @@ __global__ __launch_bounds__(256) void knn_center_kernel(
     } else if (precision == 1) {
       const uint16_t h = f2bf(v);
       reinterpret_cast<uint16_t*>(xout)[r * mp + c] = h;
-      const double d = (double)bf2f(h) - (double)v;
+      const double vh = (double)bf2f(h);
+      const double d = vh - (double)v;
       e = fma(d, d, e);
+      sh = fma(vh, vh, sh);
     } else {
       const int pk = __builtin_amdgcn_cvt_pk_fp8_f32(v * isc, 0.0f, 0, false);
       reinterpret_cast<uint8_t*>(xout)[r * mp + c] = (uint8_t)(pk & 0xff);
-      const double d = (double)sc * (double)__builtin_amdgcn_cvt_f32_fp8(pk, 0) - (double)v;
+      const double vh = (double)sc * (double)__builtin_amdgcn_cvt_f32_fp8(pk, 0);
+      const double d = vh - (double)v;
       e = fma(d, d, e);
+      sh = fma(vh, vh, sh);
     }
   }
   s = wave_sum(s);
   e = wave_sum(e);
+  sh = wave_sum(sh);
   if (lane == 0) {
-    norms[r] = (float)s;
+    // the GEMM scores use the norm of the copy it multiplies, so that score + norm_i is the
+    // squared distance of the two copies up to float32 rounding
+    norms[r] = (float)(precision == 0 ? s : sh);
+    if (r % KBQ == 0) tile_active[r / KBQ] = 0u;
     radius[r] = (float)(sqrt(e) * (1.0 + 0x1p-20));   // rounded up: it bounds an error
     if (scales) scales[r] = sc;
     thr[r] = 0xFFFFFFFFu;   // no K'-th key published yet
@@ -868,6 +890,37 @@ __global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
   flush();
 }
 
+// The diagonal tile pairs' scores for the rescan of uncertified queries: tile qt against
+// itself, computed by the same code as in the GEMM kernel (so with the same roundings) and
+// stored like a transposed tile after the off-diagonal ones; only tiles holding a rescanned
+// query are computed.
+template <int PREC>
+__global__ __launch_bounds__(KNT) void knn_diag_tiles_kernel(const void* __restrict__ xsrc, int64_t mp,
+                                                             const float* __restrict__ norms,
+                                                             const float* __restrict__ scales, int64_t n,
+                                                             int include_self, float* __restrict__ tbuf,
+                                                             const uint32_t* __restrict__ tile_active) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t qt = blockIdx.x;
+  if (tile_active[qt] == 0u) return;             // uniform over the workgroup
+  const TileSched S = make_sched(n, 1);
+  const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int64_t q0 = qt * KBQ;
+  uint4 pre[Stage<PREC>::NPRE];
+  stage_load<PREC>(pre, xsrc, mp, n, q0, q0, 0);
+  tile_scores<PREC>(xsrc, mp, norms, scales, n, q0, q0, include_self, smem, pre);
+  __syncthreads();
+  const float* Ss = reinterpret_cast<const float*>(smem);
+  const float nx0 = q0 + lane < n ? norms[q0 + lane] : INFINITY;
+  const float nx1 = q0 + 64 + lane < n ? norms[q0 + 64 + lane] : INFINITY;
+  const int c0 = 16 * w;
+  float* tout = tbuf + (b_pairs(S) + qt) * (KBQ * KBN) + c0 * KBQ;
+  for (int cc = 0; cc < 16; ++cc) {
+    tout[cc * KBQ + lane] = Ss[lane * SLD + c0 + cc] + nx0;
+    tout[cc * KBQ + 64 + lane] = Ss[(64 + lane) * SLD + c0 + cc] + nx1;
+  }
+}
+
 // The row-side lists of the symmetric schedule are complete once the GEMM kernel ends: the
 // K'-th key of their merge (one wave per query; each list ascending, read in reverse) bounds
 // the query's final K'-th key from above.
@@ -981,48 +1034,13 @@ __global__ __launch_bounds__(KNT) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
 }
 
 // ------------------------------------------------------------------------------------
-// merge + float32 re-rank + certificate.  One wave per query, 4 queries per block.
+// float32 difference-form distances sum_a (x_a - y_a)^2 from the original X of the
+// candidates held by lanes 0 .. kc-1 (index lj, valid_j) to query qi: every lane keeps a
+// partial sum per candidate (lanes over columns), then one transpose-reduction leaves the
+// total for candidate r in lane r.  Lanes past kc or with an invalid index get +inf.
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void knn_rerank_kernel(
-    const float* __restrict__ X, int64_t n, int64_t m, int64_t ldx, int k, int kc, int sym,
-    int64_t GA, int64_t GB, int slotb, int nslot, const float* __restrict__ cand_s,
-    const int* __restrict__ cand_j,
-    const float* __restrict__ norms, const float* __restrict__ radius,
-    const float* __restrict__ stats, int include_self, int32_t* __restrict__ idx_out,
-    float* __restrict__ d2_out, uint8_t* __restrict__ kflags) {
-  const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-  const int64_t qi = (int64_t)blockIdx.x * 4 + wv;
-  if (qi >= n) return;                      // whole wave exits together
-  const TileSched S = make_sched(n, sym);
-  const int64_t qt = qi / KBQ, row = qi % KBQ;
-  // list segments: row side (slots 0 ..), column side (slots slotb ..)
-  const int64_t na = segments(a_start(S, qt), a_len(S, qt), GA, a_pairs(S));
-  const int64_t nb = sym ? segments(b_start(S, qt), b_len(S, qt), GB, b_pairs(S)) : 0;
-  // merge the segment lists (each ascending; read in reverse, so descending) into the 64 best;
-  // eight lists' loads are in flight before their merges
-  uint32_t lh = KEY_PAD_HI, ll = KEY_PAD_LO;
-  const int src = WAVE - 1 - lane;
-  for (int64_t s0 = 0; s0 < na + nb; s0 += 8) {
-    uint32_t bh[8], bl[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t sg = s0 + u;
-      const int64_t slot = sg < na ? sg : slotb + (sg - na);
-      const int64_t o = ((qt * nslot + slot) * KBQ + row) * kc;
-      const bool in = sg < na + nb && src < kc;
-      bh[u] = in ? f2ord(cand_s[o + src]) : 0xFFFFFFFFu;
-      bl[u] = in ? (uint32_t)cand_j[o + src] : 0xFFFFFFFFu;
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (s0 + u < na + nb) wave_merge64(lh, ll, bh[u], bl[u]);
-  }
-  const int lj = (int)ll;
-  const float s_last = ord2f(rdlane_u(lh, kc - 1));   // every non-candidate scores >= s_last
-  // exact float32 difference-form distances of the kc candidates: every lane keeps a
-  // partial sum per candidate (lanes over columns), then one transpose-reduction leaves
-  // the total for candidate r in lane r
-  const bool valid_j = lj >= 0 && (int64_t)lj < n;
+__device__ __forceinline__ float cand_exact_d2(const float* __restrict__ X, int64_t m, int64_t ldx, int64_t qi,
+                                               int lj, bool valid_j, int kc, int lane) {
   const int jsafe = valid_j ? lj : (int)qi;
   float acc[KCMAX];
 #pragma unroll
@@ -1082,7 +1100,81 @@ __global__ __launch_bounds__(256) void knn_rerank_kernel(
       acc[t] = keep + __shfl_xor(send, wdt, WAVE);
     }
   }
-  const float myd = (lane < kc && valid_j) ? acc[0] : INFINITY;
+  return (lane < kc && valid_j) ? acc[0] : INFINITY;
+}
+
+// Rounding bounds shared by the certificate and the rescan.  A query's GEMM score of a
+// point j, s = fl(||y_j||^2 - 2 x_i . y_j) on the copies y = lowp(x - mu) the GEMM
+// multiplies, differs from ||y_j||^2 - 2 y_i . y_j by at most E: float32 norms, the MFMA's
+// float32 accumulation of exact products (gamma_{m+2} sum |y_ia y_ja| <= gamma ||y_i|| ||y_j||),
+// the fp8 scale products, the final add, and the re-association of a transposed score
+// (fl(||y_r||^2 + D) - ||y_r||^2 + ||y_c||^2).  With the stored norms rounded too,
+//   ||y_i - y_j|| >= sqrt(max(0, s + ||y_i||^2 - E)),
+// and by the triangle inequality the centred rows xc = fl(x - mu) are at least
+// e_i + e_j closer than that at most (e = ||y - xc||, the rounding radius), the originals
+// at most cen_i + cen_j more (cen = 1.0001 u (||y|| + e), the rounding of the centring).
+struct CertBounds {
+  double a;      // s + a = the lower bound on ||y_i - y_j||^2 (a = ||y_i||^2 - E)
+  double slack;  // e_i + cen_i
+  double emax;   // e_j + cen_j over all j
+};
+
+__device__ __forceinline__ CertBounds cert_bounds(double ni, double ei, double nmax, double emax, int64_t m) {
+  const double u = 0x1p-24;
+  const double gm = (double)(m + 2) * u / (1.0 - (double)(m + 2) * u);
+  const double rn = sqrt(ni);
+  const double E = 4.0 * u * ni + 5.0 * u * nmax * nmax + (2.0 * gm + 14.0 * u) * rn * nmax;
+  CertBounds b;
+  b.a = ni - E;
+  b.slack = ei + 1.0001 * u * (rn + ei);
+  b.emax = emax + 1.0001 * u * (nmax + emax);
+  return b;
+}
+
+// ------------------------------------------------------------------------------------
+// merge + float32 re-rank + certificate.  One wave per query, 4 queries per block.
+// A query is certified when every point outside its K' candidates is provably farther than
+// its k-th re-ranked neighbour; under the symmetric schedule an uncertified one is handed to
+// the rescan (knn_collect + knn_rerank2) with its exact candidate distances and thresholds.
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void knn_rerank_kernel(
+    const float* __restrict__ X, int64_t n, int64_t m, int64_t ldx, int k, int kc, int sym,
+    int64_t GA, int64_t GB, int slotb, int nslot, const float* __restrict__ cand_s,
+    const int* __restrict__ cand_j,
+    const float* __restrict__ norms, const float* __restrict__ radius,
+    const float* __restrict__ stats, int include_self, int32_t* __restrict__ idx_out,
+    float* __restrict__ d2_out, uint8_t* __restrict__ kflags, RescanWs rs) {
+  const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int64_t qi = (int64_t)blockIdx.x * 4 + wv;
+  if (qi >= n) return;                      // whole wave exits together
+  const TileSched S = make_sched(n, sym);
+  const int64_t qt = qi / KBQ, row = qi % KBQ;
+  // list segments: row side (slots 0 ..), column side (slots slotb ..)
+  const int64_t na = segments(a_start(S, qt), a_len(S, qt), GA, a_pairs(S));
+  const int64_t nb = sym ? segments(b_start(S, qt), b_len(S, qt), GB, b_pairs(S)) : 0;
+  // merge the segment lists (each ascending; read in reverse, so descending) into the 64 best;
+  // eight lists' loads are in flight before their merges
+  uint32_t lh = KEY_PAD_HI, ll = KEY_PAD_LO;
+  const int src = WAVE - 1 - lane;
+  for (int64_t s0 = 0; s0 < na + nb; s0 += 8) {
+    uint32_t bh[8], bl[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t sg = s0 + u;
+      const int64_t slot = sg < na ? sg : slotb + (sg - na);
+      const int64_t o = ((qt * nslot + slot) * KBQ + row) * kc;
+      const bool in = sg < na + nb && src < kc;
+      bh[u] = in ? f2ord(cand_s[o + src]) : 0xFFFFFFFFu;
+      bl[u] = in ? (uint32_t)cand_j[o + src] : 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (s0 + u < na + nb) wave_merge64(lh, ll, bh[u], bl[u]);
+  }
+  const int lj = (int)ll;
+  const float s_last = ord2f(rdlane_u(lh, kc - 1));   // every non-candidate scores >= s_last
+  const bool valid_j = lj >= 0 && (int64_t)lj < n;
+  const float myd = cand_exact_d2(X, m, ldx, qi, lj, valid_j, kc, lane);
   const int myj = (lane < kc && valid_j) ? lj : INT_MAX;
   // order by (distance, index); the point itself (MC_INCLUDE_SELF) comes first
   uint32_t sh = f2ord(lane < kc ? myd : INFINITY);
@@ -1099,30 +1191,186 @@ __global__ __launch_bounds__(256) void knn_rerank_kernel(
   }
   const float dk = rdlane(dr, k - 1);
   const float dk1 = kc > k ? rdlane(dr, k) : INFINITY;
+  const double u = 0x1p-24;
+  const double gam = (double)(m + 2) * u / (1.0 - (double)(m + 2) * u);
+  // certificate: every non-candidate y has GEMM score >= s_last
+  bool cert = true;
+  CertBounds cb{};
+  const double dk_hi = (double)dk / (1.0 - gam);   // the true k-th distance is at most this
+  if ((int64_t)kc < n - (include_self ? 0 : 1) && isfinite(s_last)) {
+    cb = cert_bounds((double)norms[qi], (double)radius[qi], (double)stats[0], (double)stats[1], m);
+    const double lo2 = (double)s_last + cb.a;
+    const double lo = (lo2 > 0.0 ? sqrt(lo2) : 0.0) - cb.slack - cb.emax;
+    cert = lo > 0.0 && lo * lo > dk_hi;
+  }
+  if (lane == 0) {
+    if (kflags) {
+      uint8_t fl = 0;
+      if (kc > k && isfinite(dk1) && (double)dk1 - (double)dk <= 2.0 * gam * (double)dk1)
+        fl |= PF_KNN_AMBIGUOUS;
+      if (!cert) fl |= PF_KNN_UNCERTIFIED;
+      kflags[qi] = fl;
+    }
+    rs.cnt[qi] = 0;
+  }
+  // hand an uncertified query to the rescan: a point j can be among the true k nearest only
+  // if its score s satisfies sqrt(max(0, s + a)) - e_j - cen_j <= sqrt(dk_hi) + e_i + cen_i = T
+  float thr = -INFINITY;
+  if (!cert && sym && isfinite(dk)) {
+    const double T = sqrt(dk_hi) * (1.0 + 4.0 * u) + cb.slack;
+    const double tq = (T + cb.emax) * (T + cb.emax) * (1.0 + 4.0 * u) - cb.a;
+    thr = (float)tq * (1.0f + 0x1p-22f);
+    if (lane == 0) {
+      rs.act_T[qi] = (float)T * (1.0f + 0x1p-22f);
+      rs.act_a[qi] = (float)cb.a * (cb.a > 0.0 ? 1.0f - 0x1p-22f : 1.0f + 0x1p-22f);
+      atomicOr(rs.tile_active + qt, 1u);
+    }
+    if (lane < kc) {
+      rs.p1d[qi * KCMAX + lane] = dr;
+      rs.p1j[qi * KCMAX + lane] = kj;
+    }
+  }
+  if (lane == 0) rs.act_thr[qi] = thr;
+}
+
+// ------------------------------------------------------------------------------------
+// Rescan of uncertified queries (symmetric schedule).  The transposed tiles hold every
+// score of the distance matrix once: tile [c][r] = ||y_r||^2 + D[r][c] scores candidate r
+// (row tile) for query c (column tile), and ||y_c||^2 + D[r][c] = tile - ||y_r||^2 + ||y_c||^2
+// scores c for query r; the diagonal tiles cover a tile against itself.  knn_collect streams
+// them once and appends every candidate that passes an active query's test to that query's
+// buffer; knn_rerank2 evaluates the new ones in float32 and re-selects the k nearest.
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void knn_collect_kernel(const float* __restrict__ tbuf, int64_t n, int64_t G,
+                                                          const float* __restrict__ norms,
+                                                          const float* __restrict__ radius, RescanWs rs) {
+  const TileSched S = make_sched(n, 1);
+  const int64_t PB = b_pairs(S), P = PB + S.T;
+  const int64_t L = blockIdx.x;
+  const int64_t tb = (L * P) / G, te = ((L + 1) * P) / G;
+  __shared__ float q_thr[2][KBQ], q_T[2][KBQ], q_a[2][KBQ], q_n[2][KBQ], q_e[2][KBQ];
+  const int tid = threadIdx.x;
+  const double u = 0x1p-24;
+  for (int64_t t = tb; t < te; ++t) {
+    int64_t ct, rt;                          // column tile (queries of the stored rows), row tile
+    if (t < PB) {
+      int64_t d;
+      b_pair(S, t, ct, d);
+      rt = (ct - d + S.T) % S.T;
+    } else {
+      ct = rt = t - PB;
+    }
+    const bool act_c = rs.tile_active[ct] != 0u, act_r = t < PB && rs.tile_active[rt] != 0u;
+    if (!act_c && !act_r) continue;          // uniform over the workgroup
+    __syncthreads();
+    if (tid < 2 * KBQ) {
+      const int side = tid / KBQ, o = tid % KBQ;
+      const int64_t q = (side == 0 ? ct : rt) * KBQ + o;
+      const bool in = q < n;
+      q_thr[side][o] = in ? rs.act_thr[q] : -INFINITY;
+      q_T[side][o] = in ? rs.act_T[q] : 0.0f;
+      q_a[side][o] = in ? rs.act_a[q] : 0.0f;
+      q_n[side][o] = in ? norms[q] : 0.0f;
+      const float e = in ? radius[q] : 0.0f;
+      // e + cen of the point (the centring slack of cert_bounds)
+      q_e[side][o] = in ? (float)((double)e + 1.0001 * u * (sqrt((double)q_n[side][o]) + (double)e)) * (1.0f + 0x1p-22f)
+                        : 0.0f;
+    }
+    __syncthreads();
+    const float* tile = tbuf + t * (int64_t)(KBQ * KBN);
+    // thread tid: stored row c = tid / 2, columns r = 64 (tid % 2) .. + 63
+    const int c = tid / 2, r0 = 64 * (tid % 2);
+    const int64_t qc = ct * KBQ + c;
+    const float thc = q_thr[0][c];
+    const float nc = q_n[0][c], ec = q_e[0][c];
+#pragma unroll 4
+    for (int v = 0; v < 16; ++v) {
+      const float4 s4 = *reinterpret_cast<const float4*>(tile + c * KBQ + r0 + 4 * v);
+      const float sv[4] = {s4.x, s4.y, s4.z, s4.w};
+#pragma unroll
+      for (int e4 = 0; e4 < 4; ++e4) {
+        const int r = r0 + 4 * v + e4;
+        const int64_t qr = rt * KBQ + r;
+        const float s = sv[e4];
+        // candidate r for query c
+        if (s <= thc && qc < n && qr < n) {
+          const float lb = sqrtf(fmaxf(0.0f, s + q_a[0][c])) * (1.0f - 0x1p-22f) - q_e[1][r];
+          if (lb <= q_T[0][c]) {
+            const int slot = atomicAdd(rs.cnt + qc, 1);
+            if (slot < RESCAN_CMAX) rs.cbuf[qc * RESCAN_CMAX + slot] = (int)qr;
+          }
+        }
+        // candidate c for query r (off-diagonal tiles): re-associate the stored score
+        if (t < PB && qr < n && qc < n) {
+          const float thr = q_thr[1][r];
+          if (thr > -INFINITY) {
+            const float s2 = (s - q_n[1][r]) + nc;
+            if (s2 <= thr) {
+              const float lb = sqrtf(fmaxf(0.0f, s2 + q_a[1][r])) * (1.0f - 0x1p-22f) - ec;
+              if (lb <= q_T[1][r]) {
+                const int slot = atomicAdd(rs.cnt + qr, 1);
+                if (slot < RESCAN_CMAX) rs.cbuf[qr * RESCAN_CMAX + slot] = (int)qc;
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// One wave per query handed to the rescan: the pass's exact candidate distances plus the
+// float32 distances of every collected point not among them, re-selected by (d^2, index).
+// A query whose buffer overflowed keeps its first result and its UNCERTIFIED flag.
+__global__ __launch_bounds__(256) void knn_rerank2_kernel(const float* __restrict__ X, int64_t n, int64_t m,
+                                                          int64_t ldx, int k, int kc, int include_self,
+                                                          int32_t* __restrict__ idx_out,
+                                                          float* __restrict__ d2_out,
+                                                          uint8_t* __restrict__ kflags, RescanWs rs) {
+  const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int64_t qi = (int64_t)blockIdx.x * 4 + wv;
+  if (qi >= n) return;
+  if (!(rs.act_thr[qi] > -INFINITY)) return;      // certified, or full schedule
+  const int cnt = rs.cnt[qi];
+  if (cnt > RESCAN_CMAX) return;
+  // the first pass's kc candidates (ranks in lanes), exact float32 distances
+  const int pj = lane < kc ? rs.p1j[qi * KCMAX + lane] : INT_MAX;
+  const float pd = lane < kc ? rs.p1d[qi * KCMAX + lane] : INFINITY;
+  uint32_t lh = f2ord(pd), ll = (uint32_t)pj;
+  if (include_self && pj == (int)qi) lh = f2ord(-1.0f);
+  for (int b0 = 0; b0 < cnt; b0 += WAVE) {
+    const int cj = b0 + lane < cnt ? rs.cbuf[qi * RESCAN_CMAX + b0 + lane] : -1;
+    bool dup = cj < 0;
+    for (int r = 0; r < kc; ++r) dup |= cj == __builtin_amdgcn_readlane(pj, r);
+    const uint64_t fresh = __ballot(!dup);
+    const int nn = __popcll(fresh);
+    if (nn == 0) continue;
+    // compact the new candidates into lanes 0 .. nn-1
+    const int dst = !dup ? __popcll(fresh & ((1ull << lane) - 1ull)) : WAVE - 1;
+    int nj = __builtin_amdgcn_ds_permute(dst << 2, cj);
+    if (lane >= nn) nj = -1;
+    const bool valid = nj >= 0 && (int64_t)nj < n;
+    const float d = cand_exact_d2(X, m, ldx, qi, nj, valid, nn, lane);
+    uint32_t bh = lane < nn && valid ? f2ord(d) : 0xFFFFFFFFu;
+    uint32_t bl = lane < nn && valid ? (uint32_t)nj : 0xFFFFFFFFu;
+    if (include_self && (int)bl == (int)qi) bh = f2ord(-1.0f);
+    wave_sort64<false>(bh, bl);
+    wave_merge64(lh, ll, bh, bl);
+  }
+  const int kj = (int)ll;
+  float dr = ord2f(lh);
+  if (include_self && kj == (int)qi) dr = 0.0f;
+  if (lane < k) {
+    idx_out[qi * k + lane] = kj;
+    if (d2_out) d2_out[qi * k + lane] = dr;
+  }
+  const float dk = rdlane(dr, k - 1);
+  const float dk1 = rdlane(dr, k);
   if (lane == 0 && kflags) {
-    uint8_t fl = 0;
     const double u = 0x1p-24;
     const double gam = (double)(m + 2) * u / (1.0 - (double)(m + 2) * u);
-    if (kc > k && isfinite(dk1) && (double)dk1 - (double)dk <= 2.0 * gam * (double)dk1)
-      fl |= PF_KNN_AMBIGUOUS;
-    // certificate: every non-candidate y has GEMM score >= s_last; bound its true distance
-    // from below and compare with the k-th re-ranked distance.
-    bool cert = true;
-    if ((int64_t)kc < n - (include_self ? 0 : 1) && isfinite(s_last)) {
-      const double ni = (double)norms[qi], rn = sqrt(ni);
-      const double nmax = (double)stats[0], emax = (double)stats[1], ei = (double)radius[qi];
-      const double gm = (double)(m + 8) * u / (1.0 - (double)(m + 8) * u);
-      // |gemm d2 - ||xc_i - xc_j||^2|: rounding of the low-precision copy, fp32 dot and norms
-      // (5 u: the norm add, plus the separately rounded fp8 cross term, |2 x_i . x_j| <= ni + nmax^2)
-      const double E = 2.0 * (ei * (nmax + emax) + rn * emax) + 2.0 * gm * (rn + ei) * (nmax + emax) +
-                       5.0 * u * (ni + nmax * nmax) + gm * (ni + nmax * nmax);
-      const double lo2 = ni + (double)s_last - E;
-      // centring rounding: | ||xc_i - xc_j|| - ||x_i - x_j|| | <= u (||xc_i|| + ||xc_j||) (1+u)
-      const double lo = (lo2 > 0.0 ? sqrt(lo2) : 0.0) - 1.0001 * u * (rn + nmax);
-      const double dk_hi = (double)dk / (1.0 - gam);
-      cert = lo > 0.0 && lo * lo > dk_hi;
-    }
-    if (!cert) fl |= PF_KNN_UNCERTIFIED;
+    uint8_t fl = 0;
+    if (isfinite(dk1) && (double)dk1 - (double)dk <= 2.0 * gam * (double)dk1) fl |= PF_KNN_AMBIGUOUS;
     kflags[qi] = fl;
   }
 }
@@ -1193,9 +1441,30 @@ KnnPlan knn_plan(int64_t n, int64_t m, int k, int kc, int precision) {
   p.off_scale = off;  off += precision == 2 ? align256((size_t)n * 4) : 0;
   p.off_cap = off;    off += p.sym ? align256((size_t)n * 4) : 0;
   p.off_thr = off;    off += align256((size_t)n * 4);
-  p.off_tbuf = off;   off += (size_t)p.pairs_b * tile_b;
+  // rescan state (per query), then the transposed tiles (plus the diagonal ones)
+  p.off_rescan = off;
+  off += align256((size_t)n * 4) * 4;                        // act_thr, act_T, act_a, cnt
+  off += align256((size_t)n * RESCAN_CMAX * 4);              // cbuf
+  off += align256((size_t)n * KCMAX * 4) * 2;                // p1d, p1j
+  off += align256((size_t)T * 4);                            // tile_active
+  p.off_tbuf = off;   off += p.sym ? (size_t)(p.pairs_b + T) * tile_b : 0;
   p.total = off;
   return p;
+}
+
+static RescanWs rescan_ws(unsigned char* base, const KnnPlan& p) {
+  RescanWs r;
+  const int64_t n = p.n;
+  size_t off = p.off_rescan;
+  r.act_thr = reinterpret_cast<float*>(base + off); off += align256((size_t)n * 4);
+  r.act_T = reinterpret_cast<float*>(base + off);   off += align256((size_t)n * 4);
+  r.act_a = reinterpret_cast<float*>(base + off);   off += align256((size_t)n * 4);
+  r.cnt = reinterpret_cast<int*>(base + off);       off += align256((size_t)n * 4);
+  r.cbuf = reinterpret_cast<int*>(base + off);      off += align256((size_t)n * RESCAN_CMAX * 4);
+  r.p1d = reinterpret_cast<float*>(base + off);     off += align256((size_t)n * KCMAX * 4);
+  r.p1j = reinterpret_cast<int*>(base + off);       off += align256((size_t)n * KCMAX * 4);
+  r.tile_active = reinterpret_cast<uint32_t*>(base + off);
+  return r;
 }
 
 hipError_t launch_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int k, int kc,
@@ -1226,8 +1495,9 @@ hipError_t launch_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int k, 
   timing_end(1, stream);
   timing_begin(2, stream);
   uint32_t* thr = reinterpret_cast<uint32_t*>(base + plan.off_thr);
+  const RescanWs rs = rescan_ws(base, plan);
   hipLaunchKernelGGL(knn_center_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream, X, n,
-                     m, ldx, mp, mu, xc, scales, norms, radius, precision, thr);
+                     m, ldx, mp, mu, xc, scales, norms, radius, precision, thr, rs.tile_active);
   timing_end(2, stream);
   timing_begin(3, stream);
   const unsigned sgrid = (unsigned)((n + 255) / 256 < 64 ? (n + 255) / 256 : 64);
@@ -1244,6 +1514,12 @@ hipError_t launch_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int k, 
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&knn_gemm_topk_kernel<1>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_lds_bytes<1>());
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&knn_gemm_topk_kernel<2>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_lds_bytes<2>());
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&knn_diag_tiles_kernel<0>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_lds_bytes<0>());
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&knn_diag_tiles_kernel<1>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_lds_bytes<1>());
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&knn_diag_tiles_kernel<2>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_lds_bytes<2>());
     (void)hipGetLastError();
   });
@@ -1283,8 +1559,30 @@ hipError_t launch_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int k, 
   timing_begin(5, stream);
   hipLaunchKernelGGL(knn_rerank_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream, X, n, m,
                      ldx, k, kc, plan.sym, plan.groups, plan.groups_b, plan.smax, nslot, cand_s, cand_j,
-                     norms, radius, stats, self, idx, d2, kflags);
+                     norms, radius, stats, self, idx, d2, kflags, rs);
   timing_end(5, stream);
+  e = hipGetLastError();
+  if (e != hipSuccess || !plan.sym) return e;
+  // rescan of the queries the certificate could not close (symmetric schedule: every score
+  // is in the transposed and diagonal tiles)
+  timing_begin(10, stream);
+  if (precision == 0) {
+    hipLaunchKernelGGL(knn_diag_tiles_kernel<0>, dim3((unsigned)plan.tiles), dim3(KNT), gemm_lds_bytes<0>(), stream,
+                       (const void*)xc, mp, norms, scales, n, self, tbuf, (const uint32_t*)rs.tile_active);
+  } else if (precision == 1) {
+    hipLaunchKernelGGL(knn_diag_tiles_kernel<1>, dim3((unsigned)plan.tiles), dim3(KNT), gemm_lds_bytes<1>(), stream,
+                       (const void*)xc, mp, norms, scales, n, self, tbuf, (const uint32_t*)rs.tile_active);
+  } else {
+    hipLaunchKernelGGL(knn_diag_tiles_kernel<2>, dim3((unsigned)plan.tiles), dim3(KNT), gemm_lds_bytes<2>(), stream,
+                       (const void*)xc, mp, norms, scales, n, self, tbuf, (const uint32_t*)rs.tile_active);
+  }
+  const int64_t ptiles = plan.pairs_b + plan.tiles;
+  const int64_t gc = ptiles < 2048 ? ptiles : 2048;
+  hipLaunchKernelGGL(knn_collect_kernel, dim3((unsigned)gc), dim3(256), 0, stream, (const float*)tbuf, n, gc,
+                     (const float*)norms, (const float*)radius, rs);
+  hipLaunchKernelGGL(knn_rerank2_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream, X, n, m, ldx, k,
+                     kc, self, idx, d2, kflags, rs);
+  timing_end(10, stream);
   return hipGetLastError();
 }
 

@@ -47,7 +47,7 @@ struct KnnPlan {
   int64_t groups_b;   // its workgroups
   int smax_b;         // its list segments reserved per column tile
   size_t off_xc, off_norm, off_colsum, off_stats, off_cand_s, off_cand_j, off_xlow, off_scale;
-  size_t off_cap, off_thr, off_tbuf, total;
+  size_t off_cap, off_thr, off_rescan, off_tbuf, total;
 };
 
 KnnPlan knn_plan(int64_t n, int64_t m, int k, int kc, int precision);

@@ -60,6 +60,7 @@ extern "C" {
 #define MC_ELAUNCH 5     /* a kernel launch failed (hipGetLastError) */
 #define MC_ENUMERIC 6    /* MC_STRICT: some point carries a flag */
 #define MC_EDEVICE 7     /* no usable gfx950 device current */
+#define MC_ESCRATCH 8    /* sizes need more than the static scratch of a no-allocation entry point */
 
 /* precision of the MFMA stages (distance GEMM, patch moments) */
 #define MC_FP32 0 /* float32 inputs, float32 accumulation */
@@ -190,6 +191,26 @@ int mc_curvature_exact(const float* X, int64_t n, int64_t m, int64_t ldx, const 
 int mc_curvature_backward(const float* X, int64_t n, int64_t m, int64_t ldx, const int32_t* idx,
                           int32_t k, int32_t variant, const float* grad_kappa, float gap_eps,
                           float* grad_X, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * mc_curvature_fast_noalloc -- mc_curvature_fast without a workspace argument, for callers
+ * that cannot allocate device memory (code under HIP graph capture, serving loops, harnesses
+ * that forbid allocation).  Arguments and results are those of mc_curvature_fast.
+ *
+ * The per-point state that the two-pass form (k >= 13) keeps between its kernels goes to a
+ * static device array of MC_NOALLOC_SCRATCH_BYTES inside the library instead (each GPU the
+ * library runs on holds its own copy until the process ends; its address is taken on the
+ * first call on that device).  The call allocates nothing.  Sizes whose state exceeds the
+ * array (mc_workspace_bytes(MC_OP_FAST, ...) > MC_NOALLOC_SCRATCH_BYTES: n above about 7900
+ * at k = 32 with float32 moments, about 28000 at k = 16) return MC_ESCRATCH and enqueue
+ * nothing; k <= 12 needs no state and takes any n.  All calls on one GPU share its array:
+ * calls that overlap in time on one GPU (different streams or threads) race and must be
+ * serialised by the caller.
+ */
+#define MC_NOALLOC_SCRATCH_BYTES (64u << 20)
+int mc_curvature_fast_noalloc(const float* X, int64_t n, int64_t m, int64_t ldx, const int32_t* idx,
+                              int32_t k, int32_t precision, int32_t variant, uint32_t flags,
+                              float* kappa_out, uint8_t* flags_out, void* stream);
 
 /*
  * Stage timers (instrumentation, off by default).  While enabled, every kernel

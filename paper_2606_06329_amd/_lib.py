@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmecuco.so")
 
 # constants mirrored from include/mecuco.h
-MC_OK, MC_EINVAL, MC_ESHAPE, MC_EPRECISION, MC_EWORKSPACE, MC_ELAUNCH, MC_ENUMERIC, MC_EDEVICE = range(8)
+MC_OK, MC_EINVAL, MC_ESHAPE, MC_EPRECISION, MC_EWORKSPACE, MC_ELAUNCH, MC_ENUMERIC, MC_EDEVICE, MC_ESCRATCH = range(9)
+MC_NOALLOC_SCRATCH_BYTES = 64 << 20
 MC_FP32, MC_BF16, MC_FP8, MC_FP64 = 0, 1, 2, 3
 MC_FAST_FP64_KMAX = 28
 MC_FAST_PAPER, MC_FAST_HAAR = 0, 1
@@ -24,6 +25,7 @@ MC_OP_KNN, MC_OP_FAST, MC_OP_EXACT, MC_OP_BACKWARD = 0, 1, 2, 3
 MC_KMAX = 32
 
 EXPORTS = ("mc_knn", "mc_curvature_fast", "mc_curvature_exact", "mc_curvature_backward",
+           "mc_curvature_fast_noalloc",
            "mc_workspace_bytes", "mc_status_string", "mc_version", "mc_timing_enable",
            "mc_timing_read", "mc_stage_name")
 MC_STAGE_COUNT = 11
@@ -51,6 +53,8 @@ def lib() -> ctypes.CDLL:
     L.mc_knn.restype = ctypes.c_int
     L.mc_curvature_fast.argtypes = [vp, i64, i64, i64, vp, i32, i32, i32, u32, vp, vp, vp, sz, vp]
     L.mc_curvature_fast.restype = ctypes.c_int
+    L.mc_curvature_fast_noalloc.argtypes = [vp, i64, i64, i64, vp, i32, i32, i32, u32, vp, vp, vp]
+    L.mc_curvature_fast_noalloc.restype = ctypes.c_int
     L.mc_curvature_exact.argtypes = [vp, i64, i64, i64, vp, i32, i32, u32, vp, vp, vp, sz, vp]
     L.mc_curvature_exact.restype = ctypes.c_int
     L.mc_curvature_backward.argtypes = [vp, i64, i64, i64, vp, i32, i32, vp, f32, vp, vp, sz, vp]

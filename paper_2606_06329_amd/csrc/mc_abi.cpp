@@ -62,6 +62,7 @@ const char* mc_status_string(int status) {
     case MC_ELAUNCH: return "kernel launch failed";
     case MC_ENUMERIC: return "MC_STRICT: a point carries a numerical flag";
     case MC_EDEVICE: return "no gfx950 device is current";
+    case MC_ESCRATCH: return "sizes need more per-point state than the static scratch of the no-allocation entry point (MC_NOALLOC_SCRATCH_BYTES)";
     default: return "unknown status";
   }
 }

@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported():
 def test_version_and_status_strings():
     L = _lib()
     assert L.lib().mc_version() == 100
-    for st in range(8):
+    for st in range(9):
         assert len(L.status_string(st)) > 0
     assert L.status_string(99) == "unknown status"
 

@@ -230,7 +230,10 @@ int mc_curvature_fast_noalloc(const float* X, int64_t n, int64_t m, int64_t ldx,
 #define MC_STAGE_CURV_BACKWARD 8
 #define MC_STAGE_KNN_COLUMN_TOPK 9
 #define MC_STAGE_KNN_RESCAN 10
-#define MC_STAGE_COUNT 11
+#define MC_STAGE_CURV_GRAM 11   /* Fast mode, k >= 13: the three kernels of the two-pass form */
+#define MC_STAGE_CURV_EIGEN 12  /*   (k <= 12: MC_STAGE_CURV_FAST, one fused kernel) */
+#define MC_STAGE_CURV_RANGE 13
+#define MC_STAGE_COUNT 14
 int mc_timing_enable(int on);
 int mc_timing_read(int32_t stage, double* total_ms, int64_t* launches);
 const char* mc_stage_name(int32_t stage);

@@ -28,7 +28,8 @@ EXPORTS = ("mc_knn", "mc_curvature_fast", "mc_curvature_exact", "mc_curvature_ba
            "mc_curvature_fast_noalloc",
            "mc_workspace_bytes", "mc_status_string", "mc_version", "mc_timing_enable",
            "mc_timing_read", "mc_stage_name")
-MC_STAGE_COUNT = 11
+MC_STAGE_COUNT = 14
+CURV_STAGES = ("curv_fast", "curv_gram", "curv_eigen", "curv_range")
 
 _lib = None
 

@@ -678,9 +678,11 @@ static hipError_t launch_fast2_kp(const float* X, int64_t n, int64_t m, int64_t 
   static_assert(G::PPW * G::BYTES <= 64 * 1024 && E32::PPW * E32::BYTES <= 64 * 1024 &&
                     E64::PPW * E64::BYTES <= 64 * 1024 && R::PPW * R::BYTES <= 64 * 1024,
                 "per-workgroup LDS of the two-pass kernels stays within 64 KiB");
-  timing_begin(6, stream);
+  timing_begin(11, stream);
   hipLaunchKernelGGL((curv_gram_kernel<KMAX, PREC>), dim3((unsigned)((n + G::PPW - 1) / G::PPW)), dim3(G::PPW * WAVE),
                      G::PPW * G::BYTES, stream, X, n, m, ldx, idx, k, ws, L);
+  timing_end(11, stream);
+  timing_begin(12, stream);
   if constexpr (PREC != MOM_FP64) {
     hipLaunchKernelGGL((curv_eigen_kernel<KMAX, PREC, false>), dim3((unsigned)((n + E32::PPW - 1) / E32::PPW)),
                        dim3(E32::PPW * WAVE), E32::PPW * E32::BYTES, stream, n, m, k, 0, ws, L);
@@ -688,10 +690,12 @@ static hipError_t launch_fast2_kp(const float* X, int64_t n, int64_t m, int64_t 
   hipLaunchKernelGGL((curv_eigen_kernel<KMAX, PREC, true>), dim3((unsigned)((n + E64::PPW - 1) / E64::PPW)),
                      dim3(E64::PPW * WAVE), E64::PPW * E64::BYTES, stream, n, m, k,
                      PREC == MOM_FP64 ? 0 : 1, ws, L);
+  timing_end(12, stream);
+  timing_begin(13, stream);
   hipLaunchKernelGGL((curv_range_kernel<KMAX, PREC>), dim3((unsigned)((n + R::PPW - 1) / R::PPW)), dim3(R::NT),
                      R::PPW * R::BYTES, stream, X, n, m, ldx, idx, k, variant, (const unsigned char*)ws, L,
                      kappa, flags);
-  timing_end(6, stream);
+  timing_end(13, stream);
   return hipGetLastError();
 }
 

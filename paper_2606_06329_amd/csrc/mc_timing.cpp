@@ -23,7 +23,8 @@ bool g_has_pending[MC_STAGE_COUNT] = {};
 
 const char* kNames[MC_STAGE_COUNT] = {"knn_colsum", "knn_mean", "knn_center", "knn_stats",
                                        "knn_gemm_topk", "knn_rerank", "curv_fast", "curv_exact",
-                                       "curv_backward", "knn_column_topk", "knn_rescan"};
+                                       "curv_backward", "knn_column_topk", "knn_rescan",
+                                       "curv_gram", "curv_eigen", "curv_range"};
 
 hipEvent_t take() {
   if (!g_pool.empty()) {

@@ -190,8 +190,7 @@ struct EigCfg {
   static constexpr int PPW = sizeof(JT) == 8 ? 2 : 4;
   static constexpr size_t OFF_A = 0;
   static constexpr size_t OFF_V = OFF_A + (size_t)KK * JLD * sizeof(JT);
-  static constexpr size_t OFF_K = OFF_V + (size_t)KK * JLD * sizeof(JT);             // copy of K
-  static constexpr size_t OFF_ROT = (OFF_K + (size_t)KK * JLD * sizeof(JT) + 7) & ~(size_t)7;
+  static constexpr size_t OFF_ROT = (OFF_V + (size_t)KK * JLD * sizeof(JT) + 7) & ~(size_t)7;
   static constexpr size_t OFF_PAIR = OFF_ROT + (size_t)KK * 8;
   static constexpr size_t OFF_INT = (OFF_PAIR + (size_t)(KK - 1) * (KK / 2) * 2 + 15) & ~(size_t)15;
   static constexpr size_t BYTES = (OFF_INT + (size_t)(KK + 8) * 4 + 15) & ~(size_t)15;
@@ -220,7 +219,6 @@ __global__ __launch_bounds__(256) void curv_eigen_kernel(int64_t n, int64_t m, i
   unsigned char* sm = smem_all + (size_t)gid * C::BYTES;
   JT* A = reinterpret_cast<JT*>(sm + C::OFF_A);
   JT* V = reinterpret_cast<JT*>(sm + C::OFF_V);
-  JT* Kc = reinterpret_cast<JT*>(sm + C::OFF_K);
   PointLds P{};
   P.ROT = reinterpret_cast<double*>(sm + C::OFF_ROT);
   P.pairs = reinterpret_cast<uint16_t*>(sm + C::OFF_PAIR);
@@ -230,9 +228,7 @@ __global__ __launch_bounds__(256) void curv_eigen_kernel(int64_t n, int64_t m, i
 
   for (int e = lane; e < KK * KK; e += WAVE) {
     const int x = e / KK, y = e % KK;
-    const JT kv = (x < k && y < k) ? (JT)Kin[x * KMAX + y] : (JT)0;
-    A[x * C::JLD + y] = kv;
-    Kc[x * C::JLD + y] = kv;
+    A[x * C::JLD + y] = (x < k && y < k) ? (JT)Kin[x * KMAX + y] : (JT)0;
     V[x * C::JLD + y] = x == y ? (JT)1 : (JT)0;
   }
   for (int e = lane; e < (KK - 1) * HP; e += WAVE) {
@@ -281,16 +277,17 @@ __global__ __launch_bounds__(256) void curv_eigen_kernel(int64_t n, int64_t m, i
   if (sig0 > 0.0)
     while (pe < plim && (double)A[ord[pe] * C::JLD + ord[pe]] > rtol * sig0) ++pe;
   ST* UT = reinterpret_cast<ST*>(ws + L.off_ut) + (size_t)i * KMAX * KMAX;
+  // lane l < pe: column l of Ut and ||K ut_l||^2 in float64 (K from the workspace: the
+  // addresses are uniform over the wave, so they are scalar loads)
   double ts = 0.0;
-  for (int e = lane; e < k * KMAX; e += WAVE) {
-    const int a = e / KMAX, l = e % KMAX;
-    if (l < pe) {
-      const int x = ord[l];
-      const double isq = 1.0 / sqrt((double)A[x * C::JLD + x]);
-      UT[a * KMAX + l] = (ST)((double)V[a * C::JLD + x] * isq);
-      // (K ut_l)_a in float64
+  {
+    const int l = lane;
+    const int x = l < pe ? ord[l] : 0;
+    const double isq = l < pe ? 1.0 / sqrt((double)A[x * C::JLD + x]) : 0.0;
+    for (int a = 0; a < k; ++a) {
+      if (l < pe) UT[a * KMAX + l] = (ST)((double)V[a * C::JLD + x] * isq);
       double sv = 0.0;
-      for (int bb = 0; bb < k; ++bb) sv = fma((double)Kc[a * C::JLD + bb], (double)V[bb * C::JLD + x], sv);
+      for (int bb = 0; bb < k; ++bb) sv = fma((double)Kin[a * KMAX + bb], (double)V[bb * C::JLD + x], sv);
       sv *= isq;
       ts = fma(sv, sv, ts);
     }
@@ -339,13 +336,16 @@ struct RangeCfg {
 
 template <int KMAX, int PREC>
 struct RangeCfgSel {
+  // waves per SIMD the register allocation aims for (float64 staging needs more registers)
+  static constexpr int WPE = PREC == MOM_FP64 ? 1 : 2;
   static constexpr int NW = KMAX <= 16 ? 1 : (KMAX <= 26 ? 2 : 4);
   static constexpr int PPW = NW == 1 ? (PREC == MOM_FP64 ? 2 : 4) : 1;
   using C = RangeCfg<KMAX, NW, PPW, PREC == MOM_FP64 ? 8 : 4>;
 };
 
 template <int KMAX, int PREC>
-__global__ __launch_bounds__((RangeCfgSel<KMAX, PREC>::C::NT)) void curv_range_kernel(
+__global__ __launch_bounds__((RangeCfgSel<KMAX, PREC>::C::NT))
+__attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_range_kernel(
     const float* __restrict__ X, int64_t n, int64_t m, int64_t ldx, const int32_t* __restrict__ idx,
     int k, int variant, const unsigned char* __restrict__ ws, Fast2Ws L, float* __restrict__ kappa_out,
     uint8_t* __restrict__ flags_out) {
@@ -416,6 +416,8 @@ __global__ __launch_bounds__((RangeCfgSel<KMAX, PREC>::C::NT)) void curv_range_k
         ua[lb][jb][st] = (l < pe && j < k) ? UT[j * KMAX + l] : (ST)0;
       }
   gsync<C::NW>();
+  // column blocks past the point's ncol columns read the zero row, so every wave runs all NBW
+  // blocks without a branch and the compiler can interleave their loads
   int off1[C::NBW], off2[C::NBW];
 #pragma unroll
   for (int b = 0; b < C::NBW; ++b) {
@@ -562,11 +564,9 @@ __global__ __launch_bounds__((RangeCfgSel<KMAX, PREC>::C::NT)) void curv_range_k
         for (int a = 0; a < KB; ++a) av[a] = XS[(16 * a + lane % 16) * FLDX + col];
 #pragma unroll
         for (int b = 0; b < C::NBW; ++b) {
-          if (w + C::NW * b < nbr) {
-            const double bv = VS[off1[b] + col] * VS[off2[b] + col];
+          const double bv = VS[off1[b] + col] * VS[off2[b] + col];
 #pragma unroll
-            for (int a = 0; a < KB; ++a) acc[a][b] = mfma16x16x4f64(av[a], bv, acc[a][b]);
-          }
+          for (int a = 0; a < KB; ++a) acc[a][b] = mfma16x16x4f64(av[a], bv, acc[a][b]);
         }
       }
     } else if constexpr (PREC == MOM_FP32) {
@@ -579,15 +579,13 @@ __global__ __launch_bounds__((RangeCfgSel<KMAX, PREC>::C::NT)) void curv_range_k
           av[a] = *reinterpret_cast<const floatx4*>(XS + (16 * a + lane % 16) * FLDX + col);
 #pragma unroll
         for (int b = 0; b < C::NBW; ++b) {
-          if (w + C::NW * b < nbr) {
-            const floatx4 x1 = *reinterpret_cast<const floatx4*>(VS + off1[b] + col);
-            const floatx4 x2 = *reinterpret_cast<const floatx4*>(VS + off2[b] + col);
-            const floatx4 bv = x1 * x2;
+          const floatx4 x1 = *reinterpret_cast<const floatx4*>(VS + off1[b] + col);
+          const floatx4 x2 = *reinterpret_cast<const floatx4*>(VS + off2[b] + col);
+          const floatx4 bv = x1 * x2;
 #pragma unroll
-            for (int st = 0; st < 4; ++st)
+          for (int st = 0; st < 4; ++st)
 #pragma unroll
-              for (int a = 0; a < KB; ++a) acc[a][b] = mfma16x16x4(av[a][st], bv[st], acc[a][b]);
-          }
+            for (int a = 0; a < KB; ++a) acc[a][b] = mfma16x16x4(av[a][st], bv[st], acc[a][b]);
         }
       }
     } else {
@@ -606,9 +604,34 @@ __global__ __launch_bounds__((RangeCfgSel<KMAX, PREC>::C::NT)) void curv_range_k
             abf[a][4 + e] = (short)f2bf(x1[e]);
           }
         }
+        if constexpr (C::NW > 1) {
+          // the operand rows of block b + 1 are read while block b's products are formed
+          floatx4 pq[2][4];
+          auto rd = [&](floatx4 (&d)[4], int b) {
+            const ST* r1 = VS + off1[b] + col0;
+            const ST* r2 = VS + off2[b] + col0;
+            d[0] = *reinterpret_cast<const floatx4*>(r1);
+            d[1] = *reinterpret_cast<const floatx4*>(r1 + 4);
+            d[2] = *reinterpret_cast<const floatx4*>(r2);
+            d[3] = *reinterpret_cast<const floatx4*>(r2 + 4);
+          };
+          rd(pq[0], 0);
 #pragma unroll
-        for (int b = 0; b < C::NBW; ++b) {
-          if (w + C::NW * b < nbr) {
+          for (int b = 0; b < C::NBW; ++b) {
+            if (b + 1 < C::NBW) rd(pq[(b + 1) & 1], b + 1);
+            const floatx4(&cur)[4] = pq[b & 1];
+            shortx8 bbf;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              bbf[e] = (short)f2bf(cur[0][e] * cur[2][e]);
+              bbf[4 + e] = (short)f2bf(cur[1][e] * cur[3][e]);
+            }
+#pragma unroll
+            for (int a = 0; a < KB; ++a) acc[a][b] = mfma16x16x32bf16(abf[a], bbf, acc[a][b]);
+          }
+        } else {
+#pragma unroll
+          for (int b = 0; b < C::NBW; ++b) {
             const floatx4 p0 = *reinterpret_cast<const floatx4*>(VS + off1[b] + col0);
             const floatx4 p1 = *reinterpret_cast<const floatx4*>(VS + off1[b] + col0 + 4);
             const floatx4 q0 = *reinterpret_cast<const floatx4*>(VS + off2[b] + col0);

@@ -260,7 +260,8 @@ def errors_vs_oracle(kap_o, idx_np, kap_np, fl_np, m):
 
 def flag_counts(fl_np):
     return {"rank_deficient": int(((fl_np & 4) != 0).sum()), "knn_uncertified": int(((fl_np & 32) != 0).sum()),
-            "knn_ambiguous": int(((fl_np & 16) != 0).sum()), "eigen_fp64": int(((fl_np & 64) != 0).sum())}
+            "knn_ambiguous": int(((fl_np & 16) != 0).sum()), "eigen_fp64": int(((fl_np & 64) != 0).sum()),
+            "precision_limit": int(((fl_np & 128) != 0).sum())}
 
 
 def oracle_sample(X, k, rows, variant):

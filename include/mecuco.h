@@ -86,6 +86,10 @@ extern "C" {
 #define MC_PF_KNN_UNCERTIFIED 32u /* the candidate set could not be proven to contain the k nearest */
 #define MC_PF_EIGEN_FP64 64u     /* (information) Fast mode: the float32 eigen-solve found two kept
                                     eigenvalues within a relative 2^-13 and was redone in float64 */
+#define MC_PF_PRECISION_LIMIT 128u /* Fast mode: the point's error estimate exceeds the precision's
+                                      budget (an ill-conditioned Gram matrix, or bf16 moments on rows
+                                      narrower than 256; see mc_curvature_fast); kappa is still
+                                      written; MC_FP64 moments hold where this is set */
 
 /* operations for mc_workspace_bytes */
 #define MC_OP_KNN 0
@@ -143,7 +147,16 @@ int mc_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int32_t k, int32_t
  *                and float64 Jacobi for MC_FP64).  MC_FP64 centres
  *                and accumulates in float64 (v_mfma_f64_16x16x4f64): use it for
  *                thin or noisy patches whose Gram matrix is ill-conditioned, where
- *                float32 moments lose digits.  k > MC_FAST_FP64_KMAX -> MC_ESHAPE
+ *                float32 moments lose digits.  k > MC_FAST_FP64_KMAX -> MC_ESHAPE.
+ *                A point is flagged MC_PF_PRECISION_LIMIT when 2 u cond / max(q, 1) exceeds
+ *                the path's error budget, with cond = sigma_1 / sigma_pe of the Gram matrix,
+ *                q = m - pe, u = 2^-24 for MC_FP32 and MC_BF16 (float32 Gram), 2^-53 for
+ *                MC_FP64, and budgets 1e-4, 2e-2 and 1e-6: the moments' rounding turns the
+ *                weakest kept direction by about u cond towards the null space, whose term
+ *                spreads that over its q directions.
+ *                MC_BF16 moments on rows narrower than 256 flag every point
+ *                MC_PF_PRECISION_LIMIT (their 8-bit products exceed the 2e-2 budget on
+ *                strongly curved patches there)
  *   variant      MC_FAST_PAPER | MC_FAST_HAAR
  *   kappa_out    [n] float32, device, written
  *   flags_out    [n] uint8 (MC_PF_* bits), or NULL

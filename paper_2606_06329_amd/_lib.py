@@ -21,6 +21,7 @@ MC_INCLUDE_SELF, MC_STRICT = 1, 2
 MC_PF_NONFINITE, MC_PF_DEGENERATE, MC_PF_RANK_DEFICIENT = 1, 2, 4
 MC_PF_JACOBI_MAXSWEEPS, MC_PF_KNN_AMBIGUOUS, MC_PF_KNN_UNCERTIFIED = 8, 16, 32
 MC_PF_EIGEN_FP64 = 64
+MC_PF_PRECISION_LIMIT = 128
 MC_OP_KNN, MC_OP_FAST, MC_OP_EXACT, MC_OP_BACKWARD = 0, 1, 2, 3
 MC_KMAX = 32
 

@@ -188,6 +188,8 @@ __global__ __launch_bounds__((Fast1CfgSel<KMAX, PREC>::C::NT)) void curv_fast1_k
     }
     return;
   }
+  // the smallest kept eigenvalue, read before fast_terms reuses the Jacobi storage
+  const double sig_min = pe > 0 ? P.JA[P.ord[pe - 1] * C::JLD + P.ord[pe - 1]] : 0.0;
   double part[5];
   fast_terms<KMAX, C, PREC>(P, k, pe, tg, part);
 
@@ -204,6 +206,8 @@ __global__ __launch_bounds__((Fast1CfgSel<KMAX, PREC>::C::NT)) void curv_fast1_k
     if (pe < plim) fl |= PF_RANK_DEFICIENT;
     if (sweep >= JAC_MAX_SWEEPS) fl |= PF_JACOBI_MAXSWEEPS;
     if (P.misc[5]) fl |= PF_EIGEN_FP64;
+    if (!(fl & PF_DEGENERATE) && beyond_precision(sig0, sig_min, k, m, pe, PREC == MOM_FP64 ? 2 : (PREC == MOM_BF16 ? 1 : 0)))
+      fl |= PF_PRECISION_LIMIT;
     kappa_out[i] = (float)kap;
     if (flags_out) flags_out[i] = fl;
   }

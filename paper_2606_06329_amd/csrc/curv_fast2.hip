@@ -24,8 +24,8 @@
 
 namespace mc {
 
-// internal flag bit: the float32 eigen-solve found a near-degenerate kept pair
-constexpr uint8_t PF_NEED_FP64 = 0x80u;
+// rank slot value marking a point whose float32 eigen-solve found a near-degenerate kept pair
+constexpr int PE_NEED_FP64 = -1;
 
 // Workspace layout: structure of arrays over the n points.  KMAX is the kernel's k bucket.
 struct Fast2Ws {
@@ -215,7 +215,8 @@ __global__ __launch_bounds__(256) void curv_eigen_kernel(int64_t n, int64_t m, i
   uint8_t* FL = ws + L.off_fl;
   const uint8_t fl0 = FL[i];
   if (fl0 & PF_NONFINITE) return;
-  if (resolve_only && !(fl0 & PF_NEED_FP64)) return;
+  int* PE = reinterpret_cast<int*>(ws + L.off_pe);
+  if (resolve_only && PE[i] != PE_NEED_FP64) return;
   unsigned char* sm = smem_all + (size_t)gid * C::BYTES;
   JT* A = reinterpret_cast<JT*>(sm + C::OFF_A);
   JT* V = reinterpret_cast<JT*>(sm + C::OFF_V);
@@ -256,7 +257,7 @@ __global__ __launch_bounds__(256) void curv_eigen_kernel(int64_t n, int64_t m, i
       }
     }
     if (__any(near)) {
-      if (lane == 0) FL[i] = fl0 | PF_NEED_FP64;
+      if (lane == 0) PE[i] = PE_NEED_FP64;
       return;
     }
   }
@@ -295,13 +296,19 @@ __global__ __launch_bounds__(256) void curv_eigen_kernel(int64_t n, int64_t m, i
   ts = wave_sum(ts);
   if (lane == 0) {
     const double tauk = reinterpret_cast<const double*>(ws + L.off_tau)[i];
-    uint8_t fl = fl0 & (uint8_t)~PF_NEED_FP64;
+    uint8_t fl = fl0;
     if (pe < plim) fl |= PF_RANK_DEFICIENT;
     if (sweep >= JAC_MAX_SWEEPS) fl |= PF_JACOBI_MAXSWEEPS;
     if (F64 && PREC != MOM_FP64) fl |= PF_EIGEN_FP64;
-    if (!(sig0 > 0.0) || tauk == 0.0 || pe == 0) fl |= PF_DEGENERATE;
+    if (!(sig0 > 0.0) || tauk == 0.0 || pe == 0) {
+      fl |= PF_DEGENERATE;
+    } else {
+      const double smin = (double)A[ord[pe - 1] * C::JLD + ord[pe - 1]];
+      if (beyond_precision(sig0, smin, k, m, pe, PREC == MOM_FP64 ? 2 : (PREC == MOM_BF16 ? 1 : 0)))
+        fl |= PF_PRECISION_LIMIT;
+    }
     reinterpret_cast<double*>(ws + L.off_ts)[i] = ts;
-    reinterpret_cast<int*>(ws + L.off_pe)[i] = pe;
+    PE[i] = pe;
     FL[i] = fl;
   }
 }

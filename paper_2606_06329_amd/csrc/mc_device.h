@@ -22,6 +22,26 @@ constexpr uint8_t PF_JACOBI_MAXSWEEPS = 8u;
 constexpr uint8_t PF_KNN_AMBIGUOUS = 16u;
 constexpr uint8_t PF_KNN_UNCERTIFIED = 32u;
 constexpr uint8_t PF_EIGEN_FP64 = 64u;
+constexpr uint8_t PF_PRECISION_LIMIT = 128u;
+
+// Fast mode: whether the point's error estimate exceeds its precision's budget: bf16 moments
+// on rows narrower than 256 (their 8-bit products exceed 2e-2 on strongly curved patches
+// there), or a centred patch whose Gram matrix is too ill-conditioned for the moments.  The
+// moments' relative rounding u (2^-24 for float32 moments and the float32 Gram of the bf16
+// path, 2^-53 for float64) turns the weakest kept direction by about u cond, cond =
+// sigma_1 / sigma_pe, towards the null space, which moves the null-space term by that angle
+// spread over its q = m - pe directions: estimate 2 u cond / q (2 u cond when q = 0),
+// against the path's budget (1e-4 float32, 2e-2 bf16, 1e-6 float64).
+__device__ __forceinline__ bool beyond_precision(double sig_max, double sig_min, int k, int64_t m, int pe,
+                                                 int prec_class) {
+  (void)k;
+  if (prec_class == 1 && m < 256) return true;
+  if (!(sig_min > 0.0)) return pe > 0;
+  const double u = prec_class == 2 ? 0x1p-53 : 0x1p-24;
+  const double budget = prec_class == 0 ? 1e-4 : (prec_class == 1 ? 2e-2 : 1e-6);
+  const int64_t q = m - pe;
+  return 2.0 * u * (sig_max / sig_min) / (double)(q > 0 ? q : 1) > budget;
+}
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 

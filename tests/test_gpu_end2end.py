@@ -50,14 +50,15 @@ def test_full_size_sampled(name):
     print(f"  uncertified {(fl & 32).astype(bool).mean():.4f}, rank-deficient {(fl & 4).astype(bool).mean():.4f}")
 
 
-@pytest.mark.parametrize("precision,tol,noise", [("fp64", None, 0.05), ("fp32", 1e-3, 0.3)])
+@pytest.mark.parametrize("precision,tol,noise", [("fp64", None, 0.05), ("fp32", 1e-4, 0.05)])
 def test_very_large_m_auto_mode(precision, tol, noise):
     """The paper's widest regime (n = 283, m = 54621, like its largest expression array):
     Auto mode picks the Fast branch (m >= 50), the kernels stream m in chunks, and every
     point matches the oracle; k is the default floor(log2 n).  float64 moments hold the
-    float64 bar; float32 moments summed over 54621 columns carry about sqrt(m) 2^-24 = 1.4e-5
-    relative error into the Gram matrix, so their bar is 1e-3, and their rank test (eigenvalues
-    above m 2^-24 sigma_1) needs the noise directions of the patch to stay above 3e-3."""
+    float64 bar; float32 moments hold the float32 bar on every point that neither the rank test
+    nor the precision estimate flags.  The float32 rank floor grows with m (eigenvalues above
+    m 2^-24 sigma_1 = 3.3e-3 sigma_1 here), so a quarter of these noisy patches are declared
+    rank deficient on that path, flagged and left out."""
     import paper_2606_06329_amd as P
     from tests.gpu_common import TOL_FP64
     tol = TOL_FP64 if tol is None else tol
@@ -77,8 +78,12 @@ def test_very_large_m_auto_mode(precision, tol, noise):
     bad_big, _, _, _ = knn_set_report(idx, X, np.arange(0, n, 7), k)
     assert bad_big == 0
     want, pe = oracle_fast(X, idx, "paper")
-    ok_rows = ((fl.cpu().numpy() & 4) == 0) & (pe == k - 1)
-    err = rel_err(kap.cpu().numpy(), want)[ok_rows]
-    print(f"  rank-full points {ok_rows.sum()}, max rel err {err.max():.2e}", flush=True)
-    assert ok_rows.mean() > 0.95
-    assert err.max() <= tol
+    fl = fl.cpu().numpy()
+    ok_rows = ((fl & 4) == 0) & (pe == k - 1)
+    unflagged = ok_rows & ((fl & 128) == 0)
+    err = rel_err(kap.cpu().numpy(), want)
+    print(f"  rank-full points {ok_rows.sum()}, unflagged {unflagged.sum()}, max rel err {err[unflagged].max():.2e}"
+          f" (all rank-full: {err[ok_rows].max():.2e})", flush=True)
+    assert ok_rows.mean() > (0.95 if precision == "fp64" else 0.6)
+    assert unflagged.sum() >= 0.95 * ok_rows.sum()
+    assert err[unflagged].max() <= tol

@@ -76,9 +76,20 @@ def test_exact_equals_fast_haar_when_q_is_one():
     # float64-moment Fast HAAR against the exact path, both on the GPU
     kh64, _ = P.curvature_fast(to_dev(X), idd, "haar", "fp64")
     assert rel_err(ke, kh64.cpu().numpy()).max() <= TOL_FP32
-    # the float32-moment Fast path is looser on these thin (m = k), noisy patches: the Gram
-    # matrix has condition ~1e4, so float32 moments carry ~1e-3 relative error into t_null
-    assert np.median(rel_err(kh[::7], want)) <= 1e-3
+    # the float32-moment Fast path on these thin (m = k, q = 1), noisy patches: the Gram matrix
+    # has condition up to ~1e4, which float32 moments and the 1/q null term amplify past the
+    # 1e-4 bar, so those points carry MC_PF_PRECISION_LIMIT; every unflagged point holds 1e-4
+    from paper_2606_06329_amd._lib import MC_PF_PRECISION_LIMIT
+    _, fl32 = P.curvature_fast(to_dev(X), idd, "haar")
+    fl32 = fl32.cpu().numpy()[::7]
+    flagged = (fl32 & MC_PF_PRECISION_LIMIT) != 0
+    err = rel_err(kh[::7], want)
+    print(f"  float32 thin patches (Gram condition 8.6e3 .. 1.2e6): {flagged.sum()} of {len(err)} flagged, "
+          f"max error {err.max():.2e}, unflagged max {err[~flagged].max() if (~flagged).any() else 0:.2e}",
+          flush=True)
+    # no silent miss: every point beyond the float32 bar carries the flag
+    assert np.all(flagged | (err <= TOL_FP32))
+    assert np.any(err > TOL_FP32)      # the case does exceed the bar where it is flagged
 
 
 def test_exact_shape_limit():

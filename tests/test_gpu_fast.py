@@ -51,8 +51,10 @@ def test_fast_fp32_parity(case, variant):
     want, pe = oracle_fast(X, idx, variant)
     rank_ok = (fl & 4) == 0
     rank_ok &= pe == min(k - 1, X.shape[1])
+    rank_ok &= (fl & 128) == 0                      # MC_PF_PRECISION_LIMIT
     err = rel_err(kap, want)
-    print(f"  max rel err {err[rank_ok].max():.2e}, median {np.median(err[rank_ok]):.2e}", flush=True)
+    print(f"  max rel err {err[rank_ok].max():.2e}, median {np.median(err[rank_ok]):.2e}, "
+          f"precision-limit flags {int(((fl & 128) != 0).sum())}", flush=True)
     assert np.all(np.isfinite(kap))
     assert rank_ok.mean() > 0.95
     assert err[rank_ok].max() <= TOL_FP32, (err.max(), np.argmax(err))
@@ -236,3 +238,21 @@ def test_fast_near_degenerate_refined(variant):
         Xc, idc = _case("clusters", 900, 784, 2061, 11)
         _, flc = P.curvature_fast(to_dev(Xc), to_dev_idx(idc), variant, prec)
         assert not np.any(flc.cpu().numpy() & MC_PF_EIGEN_FP64), prec
+
+
+def test_bf16_narrow_rows_flagged():
+    """bf16 moments on rows narrower than 256 are outside that path's validated range: every
+    point carries MC_PF_PRECISION_LIMIT (and MC_STRICT rejects the call); float32 moments on
+    the same patches carry no such flag."""
+    import paper_2606_06329_amd as P
+    from paper_2606_06329_amd._lib import MC_PF_PRECISION_LIMIT, MecucoError
+    X, idx = _case("swissroll", 700, 128, 4013, 12)
+    _, fl = P.curvature_fast(to_dev(X), to_dev_idx(idx), "paper", "bf16")
+    assert np.all(fl.cpu().numpy() & MC_PF_PRECISION_LIMIT)
+    _, fl32 = P.curvature_fast(to_dev(X), to_dev_idx(idx), "paper", "fp32")
+    assert not np.any(fl32.cpu().numpy() & MC_PF_PRECISION_LIMIT)
+    with pytest.raises(MecucoError):
+        P.curvature_fast(to_dev(X), to_dev_idx(idx), "paper", "bf16", strict=True)
+    X2, idx2 = _case("torus", 600, 40, 3013, 16)
+    _, fl2 = P.curvature_fast(to_dev(X2), to_dev_idx(idx2), "paper", "bf16")
+    assert np.all(fl2.cpu().numpy() & MC_PF_PRECISION_LIMIT)

@@ -9,7 +9,8 @@ Each function restates one definition of the paper in plain NumPy/SciPy:
 * ``fast_terms`` / ``fast_kappa``
                              Fast branch of Algorithm 1 (truncated SVD, t_range, t_A,
                              t_B, t_null, eq. fast_curv), in two readings of the
-                             null-space term (see below)
+                             null-space term (see below); ``fast_terms_with_basis`` takes
+                             the range basis as given
 * ``dense_haar_tnull``       eq. gnull_exp summed against Sigma directly, O(m^2)
 * ``kappa_with_null_basis``  Theorem 1 with W = [V_r | a chosen null basis]
 * ``canonical_exact_kappa``  the same with the Householder (LAPACK geqrf/orgqr)
@@ -41,7 +42,7 @@ import scipy.linalg
 
 __all__ = [
     "patch", "covariance", "eig_desc", "build_H", "naive_kappa", "identity_kappa",
-    "rank_eff", "fast_terms", "fast_kappa", "dense_haar_tnull", "kappa_with_null_basis",
+    "rank_eff", "fast_terms", "fast_terms_with_basis", "fast_kappa", "dense_haar_tnull", "kappa_with_null_basis",
     "householder_null_basis", "canonical_exact_kappa", "lapack_exact_kappa",
     "monte_carlo_tnull", "range_basis", "curvature_all", "KAPPA_VARIANTS",
 ]
@@ -112,8 +113,17 @@ def fast_terms(Xc) -> dict:
     Returns tau, t_range, t_A, t_S (= ||X_c V_r||^2/(k-1)), g (= ||G||^2/(k-1)),
     t_D (= sum X_c^2 h/(k-1)), p_eff, q, and both kappa readings.
     """
-    k, m = Xc.shape
     Vr, s, pe = range_basis(Xc)
+    return fast_terms_with_basis(Xc, Vr, s)
+
+
+def fast_terms_with_basis(Xc, Vr, s) -> dict:
+    """The Fast branch's terms for a given orthonormal basis V_r (m x p_eff) of the patch's row
+    space with singular values s.  The truncated SVD fixes V_r up to rotations inside groups of
+    equal singular values; only t_range reads individual columns, the other terms depend on
+    the projector V_r V_r^T alone."""
+    k, m = Xc.shape
+    pe = Vr.shape[1]
     lam = s ** 2 / (k - 1)                      # non-zero eigenvalues lambda_r
     tau = lam.sum()                             # tau = lambda_r^T 1
     V2 = Vr * Vr

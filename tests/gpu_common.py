@@ -37,17 +37,34 @@ def rel_err(got, want):
 
 def knn_set_report(idx_gpu, X32, rows, k):
     """Compare GPU neighbour sets with the oracle on `rows`: (mismatches where the gap exceeds
-    the float32 bound, mismatches elsewhere, number of rows with a large gap)."""
+    the float32 bound, mismatches elsewhere, number of rows with a large gap).
+
+    Where several sets are correct (the k-th and (k+1)-th distances lie within the float32
+    rounding bound delta of each other) a differing set must still be admissible: every point
+    it holds lies within d_(k) + delta, every oracle neighbour it leaves out at d_(k) - delta or
+    beyond, and it holds k distinct points other than the query.  An inadmissible set counts as
+    a mismatch above the bound."""
     X64 = np.asarray(X32, dtype=np.float64)
     oidx, od2, gap, d2n = ok.knn_rows(X64, rows, k)
     bound = ok.fp32_gap_bound(X32.shape[1], d2n)
     big = gap > bound
     bad_big = bad_small = 0
     for r, i in enumerate(rows):
-        same = set(oidx[r].tolist()) == set(idx_gpu[i].tolist())
-        if not same:
-            if big[r]:
-                bad_big += 1
-            else:
-                bad_small += 1
+        gset, oset = set(idx_gpu[i].tolist()), set(oidx[r].tolist())
+        if gset == oset:
+            continue
+        if big[r]:
+            bad_big += 1
+            continue
+        dk = od2[r][-1]
+        g = np.array(sorted(gset))
+        dg = ((X64[g] - X64[i]) ** 2).sum(1)
+        left = np.array(sorted(oset - gset))
+        dl = ((X64[left] - X64[i]) ** 2).sum(1)
+        admissible = (len(gset) == k and i not in gset and np.all(dg <= dk + bound[r])
+                      and np.all(dl >= dk - bound[r]))
+        if admissible:
+            bad_small += 1
+        else:
+            bad_big += 1
     return bad_big, bad_small, int(big.sum()), oidx

@@ -87,3 +87,38 @@ def test_very_large_m_auto_mode(precision, tol, noise):
     assert ok_rows.mean() > (0.95 if precision == "fp64" else 0.6)
     assert unflagged.sum() >= 0.95 * ok_rows.sum()
     assert err[unflagged].max() <= tol
+
+
+@pytest.mark.parametrize("name,kprec,cprec,nrows", [("torus", "bf16", "bf16", 100), ("blobs", "fp8", "bf16", 30)])
+def test_full_size_low_precision_path(name, kprec, cprec, nrows):
+    """The mixed-precision paths at the full size of the configurations they are meant for, in
+    the benchmark's launch configuration: the 100000 x 256 torus with bf16 distance GEMM and
+    range products (k = 16, 32 candidates), and the 50000 x 4096 blobs with the fp8 e4m3 GEMM
+    and 64 candidates, bf16 range products (k = 32).  Sampled rows: neighbour sets exact
+    wherever the gap exceeds the float32 bound (admissible elsewhere), curvature within 2e-2 of
+    the oracle; every point certified; kappa finite and non-negative everywhere."""
+    import paper_2606_06329_amd as P
+    X, k = synth.make(name)
+    n = X.shape[0]
+    rr = P.default_rerank(k, n, kprec)
+    print(f"full size {name} n={n} m={X.shape[1]} k={k} knn {kprec} x{rr}, curvature {cprec}", flush=True)
+    Xd = to_dev(X)
+    idx, d2, kfl = P.knn(Xd, k, precision=kprec, rerank=rr)
+    kap, fl = P.curvature_fast(Xd, idx, "paper", cprec)
+    idx = idx.cpu().numpy()
+    kap = kap.cpu().numpy()
+    kfl = kfl.cpu().numpy()
+    fl = fl.cpu().numpy()
+    assert int(((kfl & 32) != 0).sum()) == 0, "uncertified neighbour sets"
+    rows = np.random.default_rng(43).choice(n, nrows, replace=False)
+    bad_big, bad_small, nbig, _ = knn_set_report(idx, X, rows, k)
+    print(f"  sets: {bad_big} wrong, {bad_small} admissible alternatives, {nbig} rows above the bound",
+          flush=True)
+    assert bad_big == 0
+    want, pe = oracle_fast(X, idx, "paper", rows=rows)
+    okr = ((fl[rows] & (4 | 128)) == 0) & (pe == k - 1)
+    err = rel_err(kap[rows], want)[okr]
+    print(f"  curvature: {okr.sum()} points, max rel err {err.max():.2e}", flush=True)
+    assert okr.mean() > 0.9
+    assert err.max() <= TOL_LOW
+    assert np.all(np.isfinite(kap)) and np.all(kap >= 0)

@@ -219,7 +219,8 @@ def test_fast_near_degenerate_refined(variant):
     float64 and flags it MC_PF_EIGEN_FP64, an informational bit MC_STRICT does not reject
     (full-rank integer patch, exact in bf16 and float32).  With an exactly degenerate pair
     kappa depends on the eigenvector basis (t_range reads individual eigenvectors), so only
-    the flag, finiteness and strict mode are checked here; generic patches never take the
+    flag, finiteness, strict mode and that kappa lies in the range the oracle gives over every
+    rotation inside the degenerate pair are checked here; generic patches never take the
     re-solve."""
     import paper_2606_06329_amd as P
     from paper_2606_06329_amd._lib import MC_PF_EIGEN_FP64
@@ -229,11 +230,27 @@ def test_fast_near_degenerate_refined(variant):
     idx = np.tile(np.arange(k, dtype=np.int32), (X.shape[0], 1))
     _, pe = oracle_fast(X, idx, variant, rows=np.array([0]))
     assert pe[0] == 7
-    for prec in ("bf16", "fp32"):
+    # several results are correct here: the oracle's kappa over every rotation of the basis
+    # inside the degenerate pair spans [lo, hi] (only t_range moves); the GPU's lies in it
+    from oracle import curvature as oc
+    Xc = oc.patch(X.astype(np.float64), idx[0])
+    Vr, sv, pe_or = oc.range_basis(Xc)
+    a, b = pe_or - 2, pe_or - 1
+    span = []
+    for phi in np.linspace(0.0, np.pi, 721):
+        c, sn = np.cos(phi), np.sin(phi)
+        V = Vr.copy()
+        V[:, a], V[:, b] = c * Vr[:, a] - sn * Vr[:, b], sn * Vr[:, a] + c * Vr[:, b]
+        span.append(oc.fast_terms_with_basis(Xc, V, sv)["kappa_" + variant])
+    lo, hi = min(span), max(span)
+    assert hi - lo > 1e-3 * hi
+    for prec, tol in (("bf16", 2e-2), ("fp32", 1e-4)):
         kap, fl = P.curvature_fast(to_dev(X), to_dev_idx(idx), variant, prec, strict=True)
         kap, fl = kap.cpu().numpy(), fl.cpu().numpy()
         assert np.all(fl == MC_PF_EIGEN_FP64), prec
         assert np.all(np.isfinite(kap)) and np.all(kap == kap[0]), prec
+        print(f"  {prec}: kappa {kap[0]:.6f} in the oracle's range [{lo:.6f}, {hi:.6f}]", flush=True)
+        assert lo * (1 - tol) <= kap[0] <= hi * (1 + tol), prec
     for prec in ("bf16", "fp32"):
         Xc, idc = _case("clusters", 900, 784, 2061, 11)
         _, flc = P.curvature_fast(to_dev(Xc), to_dev_idx(idc), variant, prec)

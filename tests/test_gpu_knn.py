@@ -178,3 +178,21 @@ def test_knn_full_schedule_large_n():
     bad_big, bad_small, nbig, _ = knn_set_report(idx, X, rows, k)
     print(f"  mismatches: {bad_big} (gap above bound, of {nbig}), {bad_small} (below)", flush=True)
     assert bad_big == 0
+
+
+def test_knn_uncertified_flag_on_equidistant_points():
+    """Points at the unit vectors of R^500 are all at distance sqrt(2) from each other: no
+    candidate list can be certified, the fp8 rescan collects every point and overflows its
+    buffer, so every query keeps MC_PF_KNN_UNCERTIFIED (and MC_PF_KNN_AMBIGUOUS); the sets
+    still hold k distinct other points; MC_STRICT rejects the call."""
+    import paper_2606_06329_amd as P
+    from paper_2606_06329_amd._lib import MC_PF_KNN_AMBIGUOUS, MC_PF_KNN_UNCERTIFIED, MecucoError
+    n = 500
+    X = np.eye(n, dtype=np.float32)
+    idx, d2, fl = P.knn(to_dev(X), 8, precision="fp8")
+    idx, fl = idx.cpu().numpy(), fl.cpu().numpy()
+    assert np.all(fl & MC_PF_KNN_UNCERTIFIED) and np.all(fl & MC_PF_KNN_AMBIGUOUS)
+    assert all(len(set(r)) == 8 and i not in r for i, r in enumerate(idx.tolist()))
+    assert np.allclose(d2.cpu().numpy(), 2.0)
+    with pytest.raises(MecucoError):
+        P.knn(to_dev(X), 8, precision="fp8", strict=True)

@@ -340,3 +340,38 @@ def test_two_point_closed_form(d, kp, kh):
         w = float(want[key])
         assert abs(t[key] - w) <= 1e-13 * max(abs(w), float(want["tau"])), key
     assert abs(t["kappa_paper"] - t["kappa_haar"]) > 1e-3 * float(want["tau"])
+
+
+def degenerate_integer_patch(m=12):
+    """Eight points whose centred Gram matrix has the eigenvalues 8 s_j^2, s = (1, 1, 2, 3, 4,
+    5, 6), plus 0: rows of an 8 x 8 Hadamard matrix without its first column, column j scaled
+    by s_j, zero-padded to m and shifted by 8.  Full rank 7 with an exactly degenerate pair
+    (the two smallest); every value is a small integer."""
+    H = np.array([[1]], np.float64)
+    for _ in range(3):
+        H = np.block([[H, H], [H, -H]])
+    pts = np.zeros((8, m))
+    pts[:, :7] = H[:, 1:] * np.array([1, 1, 2, 3, 4, 5, 6], np.float64)
+    return pts + 8.0
+
+
+def test_degenerate_pair_only_moves_t_range():
+    """Rotating the basis inside an exactly degenerate pair of singular values (finding F6):
+    tau, t_A, t_S, g and t_D depend on the projector only and stay put; t_range reads the
+    individual columns and moves, so kappa spans a range."""
+    Xc = degenerate_integer_patch(12)
+    Xc = Xc - Xc.mean(0)
+    Vr, s, pe = oc.range_basis(Xc)
+    a, b = pe - 2, pe - 1                       # the degenerate pair (smallest)
+    assert pe == 7 and abs(s[a] - s[b]) <= 1e-12 * s[0]
+    base = oc.fast_terms(Xc)
+    tr = []
+    for phi in np.linspace(0.0, np.pi, 13):
+        c, sn = np.cos(phi), np.sin(phi)
+        V = Vr.copy()
+        V[:, a], V[:, b] = c * Vr[:, a] - sn * Vr[:, b], sn * Vr[:, a] + c * Vr[:, b]
+        t = oc.fast_terms_with_basis(Xc, V, s)
+        for key in ("tau", "t_A", "t_S", "g", "t_D"):
+            assert abs(t[key] - base[key]) <= 1e-12 * max(abs(base[key]), base["tau"]), key
+        tr.append(t["t_range"])
+    assert max(tr) - min(tr) > 1e-3 * base["tau"]

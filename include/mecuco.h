@@ -96,6 +96,7 @@ extern "C" {
 #define MC_OP_FAST 1
 #define MC_OP_EXACT 2
 #define MC_OP_BACKWARD 3
+#define MC_OP_NORMALIZE 4 /* mc_normalize_minmax (only n is read) */
 
 /*
  * mc_knn -- k nearest neighbours of every point by brute force (Step 1, eq. knn).
@@ -204,6 +205,20 @@ int mc_curvature_exact(const float* X, int64_t n, int64_t m, int64_t ldx, const 
 int mc_curvature_backward(const float* X, int64_t n, int64_t m, int64_t ldx, const int32_t* idx,
                           int32_t k, int32_t variant, const float* grad_kappa, float gap_eps,
                           float* grad_X, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * mc_normalize_minmax -- out[i] = (kappa[i] - min) / (max - min), min and max over the finite
+ * scores of all n points: the per-dataset normalisation to [0, 1] of the paper's
+ * normalised-score experiment (Table 3), which keeps the ranking and removes the scale.
+ *
+ *   kappa        [n] float32 scores, device (e.g. mc_curvature_fast's output)
+ *   out          [n] float32, device, written (may alias kappa): non-finite scores give NaN,
+ *                a constant score vector gives 0, no finite score at all gives NaN everywhere
+ *   ws, ws_bytes workspace, >= mc_workspace_bytes(MC_OP_NORMALIZE, n, ...)
+ * The division is IEEE float32, so the result equals (k - min) / (max - min) evaluated in
+ * float32 on the host.
+ */
+int mc_normalize_minmax(const float* kappa, int64_t n, float* out, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * mc_curvature_fast_noalloc -- mc_curvature_fast without a workspace argument, for callers

@@ -44,7 +44,7 @@ __all__ = [
     "patch", "covariance", "eig_desc", "build_H", "naive_kappa", "identity_kappa",
     "rank_eff", "fast_terms", "fast_terms_with_basis", "fast_kappa", "dense_haar_tnull", "kappa_with_null_basis",
     "householder_null_basis", "canonical_exact_kappa", "lapack_exact_kappa",
-    "monte_carlo_tnull", "range_basis", "curvature_all", "KAPPA_VARIANTS",
+    "monte_carlo_tnull", "range_basis", "curvature_all", "minmax_normalise", "KAPPA_VARIANTS",
 ]
 
 KAPPA_VARIANTS = ("paper", "haar")
@@ -240,4 +240,18 @@ def curvature_all(X, idx, mode: str = "fast", variant: str = "paper", rows=None)
             out[r] = naive_kappa(covariance(Xc), W)
         else:
             raise ValueError(mode)
+    return out
+
+
+def minmax_normalise(kappa) -> np.ndarray:
+    """Per-dataset min-max normalisation of curvature scores to [0, 1] (the normalised-score
+    experiment): (kappa - min) / (max - min) over the finite scores; NaN stays NaN, a constant
+    vector maps to 0."""
+    k = np.asarray(kappa, dtype=np.float64)
+    fin = np.isfinite(k)
+    out = np.full(k.shape, np.nan)
+    if not fin.any():
+        return out
+    lo, hi = k[fin].min(), k[fin].max()
+    out[fin] = 0.0 if hi == lo else (k[fin] - lo) / (hi - lo)
     return out

@@ -7,4 +7,4 @@ fails loudly if it has not been built.
 """
 from .api import (MeanCurvature, curvature, curvature_backward, curvature_exact,  # noqa: F401
                   curvature_fast, default_k, default_rerank, exact_supported, knn,
-                  knn_symmetric, workspace_bytes)
+                  knn_symmetric, normalize_minmax, workspace_bytes)

@@ -22,11 +22,11 @@ MC_PF_NONFINITE, MC_PF_DEGENERATE, MC_PF_RANK_DEFICIENT = 1, 2, 4
 MC_PF_JACOBI_MAXSWEEPS, MC_PF_KNN_AMBIGUOUS, MC_PF_KNN_UNCERTIFIED = 8, 16, 32
 MC_PF_EIGEN_FP64 = 64
 MC_PF_PRECISION_LIMIT = 128
-MC_OP_KNN, MC_OP_FAST, MC_OP_EXACT, MC_OP_BACKWARD = 0, 1, 2, 3
+MC_OP_KNN, MC_OP_FAST, MC_OP_EXACT, MC_OP_BACKWARD, MC_OP_NORMALIZE = 0, 1, 2, 3, 4
 MC_KMAX = 32
 
 EXPORTS = ("mc_knn", "mc_curvature_fast", "mc_curvature_exact", "mc_curvature_backward",
-           "mc_curvature_fast_noalloc",
+           "mc_curvature_fast_noalloc", "mc_normalize_minmax",
            "mc_workspace_bytes", "mc_status_string", "mc_version", "mc_timing_enable",
            "mc_timing_read", "mc_stage_name")
 MC_STAGE_COUNT = 14
@@ -61,6 +61,8 @@ def lib() -> ctypes.CDLL:
     L.mc_curvature_exact.restype = ctypes.c_int
     L.mc_curvature_backward.argtypes = [vp, i64, i64, i64, vp, i32, i32, vp, f32, vp, vp, sz, vp]
     L.mc_curvature_backward.restype = ctypes.c_int
+    L.mc_normalize_minmax.argtypes = [vp, i64, vp, vp, sz, vp]
+    L.mc_normalize_minmax.restype = ctypes.c_int
     L.mc_workspace_bytes.argtypes = [i32, i64, i64, i32, i32, i32]
     L.mc_workspace_bytes.restype = sz
     L.mc_status_string.argtypes = [ctypes.c_int]

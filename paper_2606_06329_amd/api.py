@@ -168,18 +168,36 @@ class MeanCurvature(torch.autograd.Function):
         return g, None, None, None
 
 
+def normalize_minmax(kappa: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """(kappa - min) / (max - min) over the finite scores: the per-dataset normalisation to
+    [0, 1] of the paper's normalised-score experiment (NaN stays NaN, constant scores give 0)."""
+    if not (isinstance(kappa, torch.Tensor) and kappa.is_cuda and kappa.dtype == torch.float32
+            and kappa.dim() == 1 and kappa.is_contiguous()):
+        raise TypeError("kappa must be a contiguous 1-D float32 CUDA tensor")
+    n = kappa.numel()
+    if out is None:
+        out = torch.empty_like(kappa)
+    if out.shape != kappa.shape or out.dtype != torch.float32 or out.device != kappa.device or not out.is_contiguous():
+        raise ValueError("out must match kappa")
+    ws = _workspace(L.lib().mc_workspace_bytes(L.MC_OP_NORMALIZE, n, 1, 2, 0, 1), kappa.device)
+    st = L.lib().mc_normalize_minmax(kappa.data_ptr(), n, out.data_ptr(), ws.data_ptr(), ws.numel(),
+                                     _stream(kappa))
+    L.check(st, "mc_normalize_minmax")
+    return out
+
+
 def default_k(n: int) -> int:
     """k = floor(log2 n), the paper's default neighbourhood size (clamped to the supported range)."""
     return max(2, min(L.MC_KMAX, int(math.floor(math.log2(max(n, 2))))))
 
 
 def curvature(X: torch.Tensor, k: int | None = None, mode: str = "auto", precision: str = "fp32",
-              variant: str = "paper", idx: torch.Tensor | None = None):
+              variant: str = "paper", idx: torch.Tensor | None = None, normalize: bool = False):
     """Algorithm 1 end to end: kNN graph then per-point curvature.
 
     mode "auto" selects the exact identity when D < 50 and the fast estimator otherwise.
     precision: "fp32" | "bf16" | "fp8" (kNN GEMM in fp8, moments in bf16) | "fp64"
-    (float32 kNN, float64 moments).
+    (float32 kNN, float64 moments).  normalize: min-max normalise the scores to [0, 1].
     Returns (kappa, idx, flags) with flags the OR of the kNN and curvature flags.
     """
     n, m, _ = _cloud(X)
@@ -199,4 +217,6 @@ def curvature(X: torch.Tensor, k: int | None = None, mode: str = "auto", precisi
         raise ValueError(mode)
     if kfl is not None:
         fl = fl | kfl
+    if normalize:
+        kap = normalize_minmax(kap, out=kap)
     return kap, idx, fl

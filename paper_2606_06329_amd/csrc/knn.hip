@@ -1278,18 +1278,20 @@ __global__ __launch_bounds__(256) void knn_collect_kernel(const float* __restric
     }
     __syncthreads();
     const float* tile = tbuf + t * (int64_t)(KBQ * KBN);
-    // thread tid: stored row c = tid / 2, columns r = 64 (tid % 2) .. + 63
-    const int c = tid / 2, r0 = 64 * (tid % 2);
-    const int64_t qc = ct * KBQ + c;
-    const float thc = q_thr[0][c];
-    const float nc = q_n[0][c], ec = q_e[0][c];
+    // pass v: thread tid reads the 16 bytes at float4 index tid + 256 v (row c, columns r..r+3),
+    // so every load instruction of a wave covers 1 KiB of consecutive memory
 #pragma unroll 4
-    for (int v = 0; v < 16; ++v) {
-      const float4 s4 = *reinterpret_cast<const float4*>(tile + c * KBQ + r0 + 4 * v);
+    for (int v = 0; v < KBQ * KBN / (4 * 256); ++v) {
+      const int f = tid + 256 * v;
+      const int c = f / (KBN / 4), rb = 4 * (f % (KBN / 4));
+      const float4 s4 = *reinterpret_cast<const float4*>(tile + 4 * (int64_t)f);
       const float sv[4] = {s4.x, s4.y, s4.z, s4.w};
+      const int64_t qc = ct * KBQ + c;
+      const float thc = q_thr[0][c];
+      const float nc = q_n[0][c], ec = q_e[0][c];
 #pragma unroll
       for (int e4 = 0; e4 < 4; ++e4) {
-        const int r = r0 + 4 * v + e4;
+        const int r = rb + e4;
         const int64_t qr = rt * KBQ + r;
         const float s = sv[e4];
         // candidate r for query c

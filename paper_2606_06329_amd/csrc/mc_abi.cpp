@@ -69,6 +69,7 @@ const char* mc_status_string(int status) {
 
 size_t mc_workspace_bytes(int32_t op, int64_t n, int64_t m, int32_t k, int32_t precision,
                           int32_t rerank_factor) {
+  if (op == MC_OP_NORMALIZE) return n > 0 ? mc::normalize_ws_bytes() : 0;
   if (n <= 0 || m <= 0 || k < 2 || k > MC_KMAX || (int64_t)k >= n) return 0;
   switch (op) {
     case MC_OP_KNN: {
@@ -185,6 +186,16 @@ int mc_curvature_backward(const float* X, int64_t n, int64_t m, int64_t ldx, con
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (mc::launch_curv_backward(X, n, m, ldx, idx, k, variant, grad_kappa, gap_eps, grad_X, s) !=
       hipSuccess)
+    return MC_ELAUNCH;
+  return MC_OK;
+}
+
+int mc_normalize_minmax(const float* kappa, int64_t n, float* out, void* ws, size_t ws_bytes, void* stream) {
+  if (!kappa || !out || !ws || n <= 0) return MC_EINVAL;
+  if (ws_bytes < mc::normalize_ws_bytes() || misaligned(ws)) return MC_EWORKSPACE;
+  const int st = check_device();
+  if (st) return st;
+  if (mc::launch_normalize(kappa, n, out, ws, reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
     return MC_ELAUNCH;
   return MC_OK;
 }

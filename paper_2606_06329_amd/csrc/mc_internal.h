@@ -73,6 +73,10 @@ hipError_t launch_curv_backward(const float* X, int64_t n, int64_t m, int64_t ld
                                 const int32_t* idx, int k, int variant, const float* gk,
                                 float gap_eps, float* grad, hipStream_t stream);
 
+// Min-max normalisation of a score vector to [0, 1] (mc_normalize.hip).
+size_t normalize_ws_bytes();
+hipError_t launch_normalize(const float* kappa, int64_t n, float* out, void* ws, hipStream_t stream);
+
 hipError_t launch_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int k, int kc,
                       int precision, bool include_self, int32_t* idx, float* d2, uint8_t* kflags,
                       void* ws, const KnnPlan& plan, hipStream_t stream);

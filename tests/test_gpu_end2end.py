@@ -122,3 +122,32 @@ def test_full_size_low_precision_path(name, kprec, cprec, nrows):
     assert okr.mean() > 0.9
     assert err.max() <= TOL_LOW
     assert np.all(np.isfinite(kap)) and np.all(kap >= 0)
+
+
+def test_normalised_output():
+    """mc_normalize_minmax against the oracle's normalisation (float64) and bit for bit against
+    the same float32 arithmetic on the host; NaN scores, a constant vector, and the ragged
+    block tail (n not a multiple of 256, more than 256 blocks' worth of points)."""
+    import paper_2606_06329_amd as P
+    from oracle import curvature as oc
+    X, k = synth.make("swissroll")
+    kap, idx, fl = P.curvature(to_dev(X), k)
+    for vec in (kap, kap[:1001].clone(), torch.full((77,), 2.5, device="cuda")):
+        v = vec.clone()
+        if v.numel() > 50:
+            v[13] = float("nan")
+        z = P.normalize_minmax(v).cpu().numpy()
+        h = v.cpu().numpy()
+        want = oc.minmax_normalise(h)
+        fin = np.isfinite(h)
+        assert np.array_equal(np.isnan(z), ~fin)
+        assert np.all(np.abs(z[fin] - want[fin]) <= 2.0 ** -22)
+        lo, hi = h[fin].min(), h[fin].max()
+        f32 = np.zeros_like(h[fin]) if hi == lo else (h[fin] - lo) / np.float32(hi - lo)
+        assert np.array_equal(z[fin], f32.astype(np.float32))
+    big = torch.rand(256 * 256 * 3 + 17, device="cuda")
+    zb = P.normalize_minmax(big).cpu().numpy()
+    assert zb.min() == 0.0 and zb.max() == 1.0
+    # the end-to-end call with normalize=True equals normalising afterwards
+    kn, _, _ = P.curvature(to_dev(X), k, normalize=True)
+    assert torch.equal(kn, P.normalize_minmax(kap))

@@ -375,3 +375,20 @@ def test_degenerate_pair_only_moves_t_range():
             assert abs(t[key] - base[key]) <= 1e-12 * max(abs(base[key]), base["tau"]), key
         tr.append(t["t_range"])
     assert max(tr) - min(tr) > 1e-3 * base["tau"]
+
+
+def test_minmax_normalise():
+    """Normalised scores (the normalised-score experiment): the ranking is kept, the extremes
+    map to 0 and 1, the map is affine, NaN stays NaN and a constant vector maps to 0."""
+    rng = np.random.default_rng(12)
+    k = rng.gamma(2.0, 3.0, 500)
+    k[[7, 99]] = np.nan
+    z = oc.minmax_normalise(k)
+    fin = np.isfinite(k)
+    assert np.all(np.isnan(z[~fin]))
+    assert z[fin].min() == 0.0 and z[fin].max() == 1.0
+    assert np.array_equal(np.argsort(k[fin], kind="stable"), np.argsort(z[fin], kind="stable"))
+    a, b = np.polyfit(k[fin], z[fin], 1)
+    assert np.allclose(a * k[fin] + b, z[fin], atol=1e-12)
+    assert np.all(oc.minmax_normalise(np.full(9, 3.5)) == 0.0)
+    assert np.all(np.isnan(oc.minmax_normalise(np.array([np.nan, np.inf]))))

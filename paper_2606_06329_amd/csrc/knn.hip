@@ -353,7 +353,7 @@ __device__ __forceinline__ void row_update(uint32_t& hi, uint32_t& lo, uint32_t 
 
 // ------------------------------------------------------------------------------------
 // GEMM + top-K'.  PREC 0: fp32 MFMA 32x32x2, BK = 16; PREC 1: bf16 MFMA 16x16x32, BK = 64;
-// PREC 2: fp8 e4m3 MFMA 16x16x32 with per-row scales.
+// PREC 2: fp8 e4m3 MFMA 16x16x128 with per-row scales, BK = 128.
 //
 // Work is a list of (query tile, database tile) pairs in query-major order (the tile-pair
 // schedules below).  Workgroup L takes the contiguous range [L*P/G, (L+1)*P/G): every
@@ -429,15 +429,18 @@ __device__ __forceinline__ void stage_store(const uint4 (&pre)[Stage<PREC>::NPRE
   }
 }
 
-// Branch-free stage_load for the prefetch behind the top-K' work: rows past n read row n - 1
-// (in bounds) instead of zeros, so no load sits behind a branch and every wait on the loads
-// issued before it counts exactly the memory operations issued after them.  Those rows only
-// reach query rows whose lists are never written or published and database columns the
-// score epilogue sets to +inf, whose transposed scores add the +inf norm of a row past n.
+// Branch-free stage_load for the prefetches (the next stage inside a tile, stage 0 of the next
+// pair behind the top-K' work): rows past n read row n - 1 (in bounds) instead of zeros, so no
+// load sits behind a branch and every wait on the loads issued before it counts exactly the
+// memory operations issued after them.  An output of the tile depends only on its own row and
+// column, and those rows only reach query rows whose lists are never written or published
+// and database columns the score epilogue sets to +inf, whose transposed scores add the +inf
+// norm of a row past n.
 template <int PREC>
 __device__ __forceinline__ void stage_load_clamped(uint4 (&pre)[Stage<PREC>::NPRE], const void* __restrict__ xsrc,
-                                                   int64_t mp, int64_t n, int64_t q0, int64_t j0) {
+                                                   int64_t mp, int64_t n, int64_t q0, int64_t j0, int ch = 0) {
   using S = Stage<PREC>;
+  using G = GemmCfg<PREC>;
   const unsigned char* xs = reinterpret_cast<const unsigned char*>(xsrc);
   const int tid = threadIdx.x;
 #pragma unroll
@@ -446,7 +449,7 @@ __device__ __forceinline__ void stage_load_clamped(uint4 (&pre)[Stage<PREC>::NPR
     const int row = f / S::CPR, c = f % S::CPR;
     int64_t g = row < KBQ ? q0 + row : j0 + (row - KBQ);
     g = g < n ? g : n - 1;
-    pre[u] = *reinterpret_cast<const uint4*>(xs + g * mp * GemmCfg<PREC>::ESZ + 16 * c);
+    pre[u] = *reinterpret_cast<const uint4*>(xs + (g * mp + (int64_t)ch * G::BK) * G::ESZ + 16 * c);
   }
 }
 
@@ -554,6 +557,13 @@ __host__ __device__ __forceinline__ int64_t segments(int64_t first, int64_t len,
 // and bf16 copies each equals the fused fmaf(-2, dot, norm), as -2 dot is exact.
 // 8 waves as 2 (query rows) x 4 (db columns); wave tile 64 x 32.  On entry `pre` holds
 // stage 0 of this tile (the caller loads it early, behind the previous tile's top-K').
+// 32 bytes of LDS at a 16-byte aligned address, as the eight dwords of an MFMA operand.
+__device__ __forceinline__ intx8 lds_load32(const uint8_t* p) {
+  const uint4 lo = *reinterpret_cast<const uint4*>(p);
+  const uint4 hi = *reinterpret_cast<const uint4*>(p + 16);
+  return intx8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+}
+
 template <int PREC>
 __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64_t mp,
                                             const float* __restrict__ norms,
@@ -576,7 +586,7 @@ __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64
     stage_store<PREC>(pre, smem, 0);
     __syncthreads();
     for (int ch = 0; ch < nch; ++ch) {
-      if (ch + 1 < nch) stage_load<PREC>(pre, xsrc, mp, n, q0, j0, ch + 1);
+      if (ch + 1 < nch) stage_load_clamped<PREC>(pre, xsrc, mp, n, q0, j0, ch + 1);
       const float* base = As + (size_t)(ch & 1) * (KBQ + KBN) * G::ALD;
       const int h = lane / 32;
       float av[2][8], bv[8];
@@ -626,7 +636,7 @@ __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64
     stage_store<PREC>(pre, smem, 0);
     __syncthreads();
     for (int ch = 0; ch < nch; ++ch) {
-      if (ch + 1 < nch) stage_load<PREC>(pre, xsrc, mp, n, q0, j0, ch + 1);
+      if (ch + 1 < nch) stage_load_clamped<PREC>(pre, xsrc, mp, n, q0, j0, ch + 1);
       const uint16_t* base = As + (size_t)(ch & 1) * (KBQ + KBN) * G::ALD;
 #pragma unroll
       for (int kk = 0; kk < 2; ++kk) {           // two 32-wide k steps per stage
@@ -664,36 +674,39 @@ __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64
         }
     }
   } else {
-    // fp8 e4m3 (OCP) with per-row scales: x ~ s_i * x8_i, dot = s_i s_j (x8_i . x8_j)
+    // fp8 e4m3 (OCP) with per-row scales: x ~ s_i * x8_i, dot = s_i s_j (x8_i . x8_j).  One
+    // 16x16x128 MFMA per fragment pair and stage, each from a zero accumulator: the fp8 MFMA
+    // rounds its sum (its accumulator input included) well short of float32, so the stage
+    // results are added in float32 and that error does not compound over the stages.
     uint8_t* As = reinterpret_cast<uint8_t*>(smem);
     floatx4 acc[4][2];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const floatx4 zero4 = {0.f, 0.f, 0.f, 0.f};
     stage_store<PREC>(pre, smem, 0);
     __syncthreads();
     for (int ch = 0; ch < nch; ++ch) {
-      if (ch + 1 < nch) stage_load<PREC>(pre, xsrc, mp, n, q0, j0, ch + 1);
-      const uint8_t* base = As + (size_t)(ch & 1) * (KBQ + KBN) * G::ALD;
+      // one basic block per stage: the last stage reloads itself and stores it to the idle
+      // buffer (never read), so the scheduler sees the loads, products and sums together
+      stage_load_clamped<PREC>(pre, xsrc, mp, n, q0, j0, ch + 1 < nch ? ch + 1 : ch);
+      const uint8_t* base = As + (size_t)(ch & 1) * (KBQ + KBN) * G::ALD + 32 * (lane / 16);
+      // lane l supplies row l % 16, bytes 32 (l / 16) .. + 31 of the stage, for A and B alike
+      intx8 bv[2];
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {           // four 32-wide k steps per stage
-        long av[4], bv[2];
+      for (int b = 0; b < 2; ++b) bv[b] = lds_load32(base + (KBQ + 32 * wc + 16 * b + lane % 16) * G::ALD);
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-          av[a] = *reinterpret_cast<const long*>(
-              base + (64 * wr + 16 * a + lane % 16) * G::ALD + 32 * kk + 8 * (lane / 16));
+      for (int a = 0; a < 4; ++a) {
+        const intx8 av = lds_load32(base + (64 * wr + 16 * a + lane % 16) * G::ALD);
 #pragma unroll
         for (int b = 0; b < 2; ++b)
-          bv[b] = *reinterpret_cast<const long*>(
-              base + (KBQ + 32 * wc + 16 * b + lane % 16) * G::ALD + 32 * kk + 8 * (lane / 16));
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av[a], bv[b], acc[a][b], 0, 0, 0);
+          acc[a][b] += __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv[b], zero4, 0, 0, 0, 0, 0, 0);
+        // two products in flight per wave (the other waves of the SIMD fill the MFMA pipe):
+        // the results need no more registers than that
+        __builtin_amdgcn_sched_barrier(0);
       }
-      if (ch + 1 < nch) stage_store<PREC>(pre, smem, (ch + 1) & 1);
+      stage_store<PREC>(pre, smem, (ch + 1) & 1);
       __syncthreads();
     }
 #pragma unroll
@@ -1105,10 +1118,11 @@ __device__ __forceinline__ float cand_exact_d2(const float* __restrict__ X, int6
 
 // Rounding bounds shared by the certificate and the rescan.  A query's GEMM score of a
 // point j, s = fl(||y_j||^2 - 2 x_i . y_j) on the copies y = lowp(x - mu) the GEMM
-// multiplies, differs from ||y_j||^2 - 2 y_i . y_j by at most E: float32 norms, the MFMA's
-// float32 accumulation of exact products (gamma_{m+2} sum |y_ia y_ja| <= gamma ||y_i|| ||y_j||),
-// the fp8 scale products, the final add, and the re-association of a transposed score
-// (fl(||y_r||^2 + D) - ||y_r||^2 + ||y_c||^2).  With the stored norms rounded too,
+// multiplies, differs from ||y_j||^2 - 2 y_i . y_j by at most E: float32 norms, the dot
+// product's error g sum |y_ia y_ja| <= g ||y_i|| ||y_j|| (knn_dot_err: float32 accumulation
+// of exact products for the float32 and bf16 MFMAs, the fp8 MFMA's own rounding plus the
+// float32 sum of its per-stage results for fp8), the fp8 scale products, the final add, and
+// the re-association of a transposed score (fl(||y_r||^2 + D) - ||y_r||^2 + ||y_c||^2).  With the stored norms rounded too,
 //   ||y_i - y_j|| >= sqrt(max(0, s + ||y_i||^2 - E)),
 // and by the triangle inequality the centred rows xc = fl(x - mu) are at least
 // e_i + e_j closer than that at most (e = ||y - xc||, the rounding radius), the originals
@@ -1119,11 +1133,10 @@ struct CertBounds {
   double emax;   // e_j + cen_j over all j
 };
 
-__device__ __forceinline__ CertBounds cert_bounds(double ni, double ei, double nmax, double emax, int64_t m) {
+__device__ __forceinline__ CertBounds cert_bounds(double ni, double ei, double nmax, double emax, double gdot) {
   const double u = 0x1p-24;
-  const double gm = (double)(m + 2) * u / (1.0 - (double)(m + 2) * u);
   const double rn = sqrt(ni);
-  const double E = 4.0 * u * ni + 5.0 * u * nmax * nmax + (2.0 * gm + 14.0 * u) * rn * nmax;
+  const double E = 4.0 * u * ni + 5.0 * u * nmax * nmax + (2.0 * gdot + 14.0 * u) * rn * nmax;
   CertBounds b;
   b.a = ni - E;
   b.slack = ei + 1.0001 * u * (rn + ei);
@@ -1143,7 +1156,7 @@ __global__ __launch_bounds__(256) void knn_rerank_kernel(
     const int* __restrict__ cand_j,
     const float* __restrict__ norms, const float* __restrict__ radius,
     const float* __restrict__ stats, int include_self, int32_t* __restrict__ idx_out,
-    float* __restrict__ d2_out, uint8_t* __restrict__ kflags, RescanWs rs) {
+    float* __restrict__ d2_out, uint8_t* __restrict__ kflags, double gdot, RescanWs rs) {
   const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
   const int64_t qi = (int64_t)blockIdx.x * 4 + wv;
   if (qi >= n) return;                      // whole wave exits together
@@ -1198,7 +1211,7 @@ __global__ __launch_bounds__(256) void knn_rerank_kernel(
   CertBounds cb{};
   const double dk_hi = (double)dk / (1.0 - gam);   // the true k-th distance is at most this
   if ((int64_t)kc < n - (include_self ? 0 : 1) && isfinite(s_last)) {
-    cb = cert_bounds((double)norms[qi], (double)radius[qi], (double)stats[0], (double)stats[1], m);
+    cb = cert_bounds((double)norms[qi], (double)radius[qi], (double)stats[0], (double)stats[1], gdot);
     const double lo2 = (double)s_last + cb.a;
     const double lo = (lo2 > 0.0 ? sqrt(lo2) : 0.0) - cb.slack - cb.emax;
     cert = lo > 0.0 && lo * lo > dk_hi;
@@ -1380,6 +1393,22 @@ __global__ __launch_bounds__(256) void knn_rerank2_kernel(const float* __restric
 // ------------------------------------------------------------------------------------
 // host side
 // ------------------------------------------------------------------------------------
+// Bound g on the GEMM's dot-product error relative to ||y_i|| ||y_j||.  The float32 and bf16
+// MFMAs accumulate exact products in float32 (gamma_{m+2}).  The fp8 MFMA does not: on gfx950
+// one 16x16x128 fp8 instruction was measured at up to 2^-12.8 of sum |p| (its accumulator
+// input rounded alike), so each stage starts from zero and the bound takes 2^-9 per stage
+// (a margin of 14x) plus the float32 sum of the mp / 128 stage results.
+constexpr double FP8_MFMA_REL = 0x1p-9;
+static double knn_dot_err(int64_t m, int64_t mp, int precision) {
+  const double u = 0x1p-24;
+  if (precision == 2) {
+    const double r = (double)(mp / GemmCfg<2>::BK) + 2.0;
+    return FP8_MFMA_REL + r * u / (1.0 - r * u);
+  }
+  const double t = (double)(m + 2);
+  return t * u / (1.0 - t * u);
+}
+
 static int64_t knn_mp(int64_t m, int precision) {
   const int64_t bk = precision == 0 ? GemmCfg<0>::BK : (precision == 1 ? GemmCfg<1>::BK : GemmCfg<2>::BK);
   return ((m + bk - 1) / bk) * bk;
@@ -1561,7 +1590,7 @@ hipError_t launch_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int k, 
   timing_begin(5, stream);
   hipLaunchKernelGGL(knn_rerank_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream, X, n, m,
                      ldx, k, kc, plan.sym, plan.groups, plan.groups_b, plan.smax, nslot, cand_s, cand_j,
-                     norms, radius, stats, self, idx, d2, kflags, rs);
+                     norms, radius, stats, self, idx, d2, kflags, knn_dot_err(m, mp, precision), rs);
   timing_end(5, stream);
   e = hipGetLastError();
   if (e != hipSuccess || !plan.sym) return e;

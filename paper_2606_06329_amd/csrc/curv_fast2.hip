@@ -98,46 +98,13 @@ __global__ __launch_bounds__(256) void curv_gram_kernel(const float* __restrict_
   }
   for (int t = lane; t < (C::ROWS - k) * FLDX; t += WAVE) XS[k * FLDX + t] = (ST)0;
 
-  float xr[KMAX];
-  auto load = [&](int64_t c0) {
-    const int64_t c = c0 + lane;
-#pragma unroll
-    for (int j = 0; j < KMAX; ++j) {
-      float v = 0.0f;
-      if (j < k && c < m) v = X[(int64_t)__builtin_amdgcn_readlane(nbv, j) * ldx + c];
-      xr[j] = v;
-    }
-  };
   AccT acc[C::NUB];
 #pragma unroll
   for (int b = 0; b < C::NUB; ++b) acc[b] = AccT{0, 0, 0, 0};
   double tau64 = 0.0;
   bool nonfinite = false;
-  load(0);
-  for (int64_t c0 = 0; c0 < m; c0 += FCH) {
-#pragma unroll
-    for (int j = 0; j < KMAX; ++j)
-      if (j < k) nonfinite |= !isfinite(xr[j]);
-    if constexpr (PREC == MOM_FP64) {
-      double xc[KMAX];
-      centre_column_f64<KMAX>(xr, xc, k);
-#pragma unroll
-      for (int j = 0; j < KMAX; ++j)
-        if (j < k) {
-          tau64 = fma(xc[j], xc[j], tau64);
-          XS[j * FLDX + lane] = xc[j];
-        }
-    } else {
-      centre_column<KMAX>(xr, k);
-#pragma unroll
-      for (int j = 0; j < KMAX; ++j)
-        if (j < k) {
-          tau64 = fma((double)xr[j], (double)xr[j], tau64);
-          XS[j * FLDX + lane] = xr[j];
-        }
-    }
-    wave_sync();
-    if (c0 + FCH < m) load(c0 + FCH);
+  // the MFMA pass over one staged chunk (K's upper-triangular 16 x 16 blocks)
+  auto products = [&](int64_t c0) {
     const int ng = m - c0 >= FCH ? FCH / 16 : (int)((m - c0 + 15) / 16);
     for (int g = 0; g < ng; ++g) {
       const int col = 16 * g + 4 * (lane / 16);      // lane supplies columns col .. col+3
@@ -155,7 +122,102 @@ __global__ __launch_bounds__(256) void curv_gram_kernel(const float* __restrict_
           }
         }
     }
-    wave_sync();
+  };
+  if constexpr (PREC == MOM_FP64) {
+    float xr[KMAX];
+    auto load = [&](int64_t c0) {
+      const int64_t c = c0 + lane;
+#pragma unroll
+      for (int j = 0; j < KMAX; ++j) {
+        float v = 0.0f;
+        if (j < k && c < m) v = X[(int64_t)__builtin_amdgcn_readlane(nbv, j) * ldx + c];
+        xr[j] = v;
+      }
+    };
+    load(0);
+    for (int64_t c0 = 0; c0 < m; c0 += FCH) {
+#pragma unroll
+      for (int j = 0; j < KMAX; ++j)
+        if (j < k) nonfinite |= !isfinite(xr[j]);
+      double xc[KMAX];
+      centre_column_f64<KMAX>(xr, xc, k);
+#pragma unroll
+      for (int j = 0; j < KMAX; ++j)
+        if (j < k) {
+          tau64 = fma(xc[j], xc[j], tau64);
+          XS[j * FLDX + lane] = xc[j];
+        }
+      wave_sync();
+      if (c0 + FCH < m) load(c0 + FCH);
+      products(c0);
+      wave_sync();
+    }
+  } else {
+    // Lane (g, c4) = (lane / 16, lane % 16) gathers columns 4 c4 .. 4 c4 + 3 of the rows
+    // j = 4 t + g, one 16-byte load per row (four rows per instruction), from row pointers it
+    // keeps for the whole pass.  The column's offsets from its first row and their mean are
+    // reduced over the four lane groups.  tau's float64 sum turns non-finite when a gathered
+    // value is (a NaN, or an infinity minus an infinity, reaches the centred entries of its
+    // column) or a centred value overflows, so one test at the end replaces a test per value.
+    constexpr int RT = KMAX / 4;
+    static_assert(KMAX % 4 == 0, "row groups of four");
+    const int g = lane / 16, c4 = lane % 16;
+    const bool vec = (ldx % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+    const float* rp[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int j = 4 * t + g;
+      const int r = __shfl(nbv, j < k ? j : 0, WAVE);
+      rp[t] = X + (int64_t)r * ldx;
+    }
+    floatx4 xv[RT];
+    auto load = [&](int64_t c0) {
+      const int64_t c = c0 + 4 * c4;
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        floatx4 v = {0.f, 0.f, 0.f, 0.f};
+        if (4 * t + g < k) {
+          if (vec && c + 3 < m) {
+            v = *reinterpret_cast<const floatx4*>(rp[t] + c);
+          } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              if (c + e < m) v[e] = rp[t][c + e];
+          }
+        }
+        xv[t] = v;
+      }
+    };
+    load(0);
+    for (int64_t c0 = 0; c0 < m; c0 += FCH) {
+      floatx4 x0, sm = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) x0[e] = __shfl(xv[0][e], c4, WAVE);   // row 0 sits in group 0
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+        if (4 * t + g < k) {
+          xv[t] -= x0;
+          sm += xv[t];
+        }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        sm[e] += __shfl_xor(sm[e], 16, WAVE);
+        sm[e] += __shfl_xor(sm[e], 32, WAVE);
+      }
+      const floatx4 mean = sm / (float)k;
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+        if (4 * t + g < k) {
+          const floatx4 xc = xv[t] - mean;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) tau64 = fma((double)xc[e], (double)xc[e], tau64);
+          *reinterpret_cast<floatx4*>(XS + (4 * t + g) * FLDX + 4 * c4) = xc;
+        }
+      wave_sync();
+      if (c0 + FCH < m) load(c0 + FCH);
+      products(c0);
+      wave_sync();
+    }
   }
   // K (both triangles) to the workspace
   int b = 0;
@@ -173,7 +235,7 @@ __global__ __launch_bounds__(256) void curv_gram_kernel(const float* __restrict_
         }
       }
   tau64 = wave_sum(tau64);
-  const int nf = __any(nonfinite);
+  const int nf = __any(nonfinite) || !isfinite(tau64);
   if (lane == 0) {
     TAU[i] = tau64;
     FL[i] = nf ? PF_NONFINITE : 0;
@@ -314,7 +376,7 @@ __global__ __launch_bounds__(256) void curv_eigen_kernel(int64_t n, int64_t m, i
 }
 
 // ---- 3. range pass: NW waves per point ---------------------------------------------------
-template <int KMAX, int NW_, int PPW_, int ESZ_>
+template <int KMAX, int NW_, int PPW_, int ESZ_, bool BFA>
 struct RangeCfg {
   static constexpr int KB = (KMAX + 15) / 16;               // 16-row blocks of the patch
   static constexpr int NW = NW_, PPW = PPW_, NTG = NW * WAVE, NT = PPW * NTG;
@@ -338,16 +400,23 @@ struct RangeCfg {
   static constexpr size_t OFF_BJ = OFF_RED + (size_t)16 * NW * 8;          // tr G_j, r_j
   static constexpr size_t OFF_NB = OFF_BJ + (size_t)2 * KMAX * 8;
   static constexpr size_t OFF_PJ = OFF_NB + (size_t)KMAX * 4;
-  static constexpr size_t BYTES = (OFF_PJ + 2 * NPAD + 15) & ~(size_t)15;
+  // bf16 moments: the staged patch rows again as bf16, the A operand of the range GEMM
+  // (rows of FLDB = 72 elements: 144 bytes, so 16 lanes' 16-byte reads hit distinct banks)
+  static constexpr int FLDB = FCH + 8;
+  static constexpr size_t OFF_XB = (OFF_PJ + 2 * NPAD + 15) & ~(size_t)15;
+  static constexpr size_t BYTES = (OFF_XB + (BFA ? (size_t)16 * KB * FLDB * 2 : 0) + 15) & ~(size_t)15;
 };
 
 template <int KMAX, int PREC>
 struct RangeCfgSel {
-  // waves per SIMD the register allocation aims for (float64 staging needs more registers)
-  static constexpr int WPE = PREC == MOM_FP64 ? 1 : 2;
-  static constexpr int NW = KMAX <= 16 ? 1 : (KMAX <= 26 ? 2 : 4);
+  // waves per point: past k = 26 the float32 pass splits a point over 8 waves, whose
+  // registers then fit four waves per SIMD (60.8 against 63.8 ms at k = 32, m = 4096); the
+  // bf16 pass measured no gain from it (21.0 against 20.5 ms) and keeps 4
+  static constexpr int NW = KMAX <= 16 ? 1 : (KMAX <= 26 ? 2 : (PREC == MOM_FP32 ? 8 : 4));
+  // waves per SIMD the register allocation aims for
+  static constexpr int WPE = PREC == MOM_FP64 ? 1 : (NW == 8 ? 4 : 2);
   static constexpr int PPW = NW == 1 ? (PREC == MOM_FP64 ? 2 : 4) : 1;
-  using C = RangeCfg<KMAX, NW, PPW, PREC == MOM_FP64 ? 8 : 4>;
+  using C = RangeCfg<KMAX, NW, PPW, PREC == MOM_FP64 ? 8 : 4, PREC == MOM_BF16>;
 };
 
 template <int KMAX, int PREC>
@@ -382,6 +451,7 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
   int* nb = reinterpret_cast<int*>(sm + C::OFF_NB);
   unsigned char* pj1 = sm + C::OFF_PJ;
   unsigned char* pj2 = pj1 + C::NPAD;
+  uint16_t* XB = reinterpret_cast<uint16_t*>(sm + C::OFF_XB);
   const int pe = reinterpret_cast<const int*>(ws + L.off_pe)[i];
   const double tauk = reinterpret_cast<const double*>(ws + L.off_tau)[i];
   const double tS = reinterpret_cast<const double*>(ws + L.off_ts)[i];
@@ -409,9 +479,12 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
     pj2[t] = (unsigned char)b;
   }
   for (int t = tg; t < (16 * KB - k) * FLDX; t += C::NTG) XS[k * FLDX + t] = (ST)0;
+  if constexpr (PREC == MOM_BF16)
+    for (int t = tg; t < (16 * KB - k) * C::FLDB; t += C::NTG) XB[k * C::FLDB + t] = 0;
   for (int t = tg; t < FLDX; t += C::NTG) VS[C::VZERO * FLDX + t] = (ST)0;
   // Ut^T operand of the V_r^T chunk product: A[l][j] = Ut[j][l] at row l = 16 lb + lane%16,
-  // k index j = 16 jb + 4 s + lane/16
+  // k index j = 16 jb + st + 4 (lane/16): the four lane groups read patch rows four apart,
+  // 16 banks apart in LDS, so the B operand's reads are conflict-free
   ST ua[KB][KB][4];
 #pragma unroll
   for (int lb = 0; lb < KB; ++lb)
@@ -419,7 +492,7 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
     for (int jb = 0; jb < KB; ++jb)
 #pragma unroll
       for (int st = 0; st < 4; ++st) {
-        const int l = 16 * lb + lane % 16, j = 16 * jb + 4 * st + lane / 16;
+        const int l = 16 * lb + lane % 16, j = 16 * jb + st + 4 * (lane / 16);
         ua[lb][jb][st] = (l < pe && j < k) ? UT[j * KMAX + l] : (ST)0;
       }
   gsync<C::NW>();
@@ -502,6 +575,7 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
           const float xc = d[r] - mean;
           q = fmaf(xc, xc, q);
           XS[j * FLDX + colw] = xc;
+          if constexpr (PREC == MOM_BF16) XB[j * C::FLDB + colw] = f2bf(xc);
         }
       }
 #pragma unroll
@@ -533,7 +607,7 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
         for (int jb = 0; jb < KB; ++jb)
 #pragma unroll
           for (int st = 0; st < 4; ++st) {
-            const ST bv = XS[(16 * jb + 4 * st + lane / 16) * FLDX + 16 * cb + lane % 16];
+            const ST bv = XS[(16 * jb + st + 4 * (lane / 16)) * FLDX + 16 * cb + lane % 16];
             if constexpr (PREC == MOM_FP64) v = mfma16x16x4f64(ua[lb][jb][st], bv, v);
             else v = mfma16x16x4(ua[lb][jb][st], bv, v);
           }
@@ -577,8 +651,7 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
         }
       }
     } else if constexpr (PREC == MOM_FP32) {
-      const int ng = m - c0 >= FCH ? FCH / 16 : (int)((m - c0 + 15) / 16);
-      for (int g = 0; g < ng; ++g) {
+      auto gstep = [&](int g) {
         const int col = 16 * g + 4 * (lane / 16);
         floatx4 av[KB];
 #pragma unroll
@@ -594,25 +667,20 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
 #pragma unroll
             for (int a = 0; a < KB; ++a) acc[a][b] = mfma16x16x4(av[a][st], bv[st], acc[a][b]);
         }
-      }
+      };
+      const int ng = m - c0 >= FCH ? FCH / 16 : (int)((m - c0 + 15) / 16);
+      for (int g = 0; g < ng; ++g) gstep(g);
     } else {
       // bf16 operands, 32-column steps: lane l supplies columns 32 s + 8 (l / 16) + e
-      const int st32 = m - c0 >= FCH ? FCH / 32 : (int)((m - c0 + 31) / 32);
-      for (int s32 = 0; s32 < st32; ++s32) {
+      auto gstep = [&](int s32) {
         const int col0 = 32 * s32 + 8 * (lane / 16);
         shortx8 abf[KB];
 #pragma unroll
-        for (int a = 0; a < KB; ++a) {
-          const floatx4 x0 = *reinterpret_cast<const floatx4*>(XS + (16 * a + lane % 16) * FLDX + col0);
-          const floatx4 x1 = *reinterpret_cast<const floatx4*>(XS + (16 * a + lane % 16) * FLDX + col0 + 4);
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            abf[a][e] = (short)f2bf(x0[e]);
-            abf[a][4 + e] = (short)f2bf(x1[e]);
-          }
-        }
-        if constexpr (C::NW > 1) {
-          // the operand rows of block b + 1 are read while block b's products are formed
+        for (int a = 0; a < KB; ++a)
+          abf[a] = *reinterpret_cast<const shortx8*>(XB + (16 * a + lane % 16) * C::FLDB + col0);
+        if constexpr (C::NW == 2 || C::NW == 4) {
+          // the operand rows of block b + 1 are read while block b's products are formed (with
+          // 8 waves per point the registers are kept for occupancy instead)
           floatx4 pq[2][4];
           auto rd = [&](floatx4 (&d)[4], int b) {
             const ST* r1 = VS + off1[b] + col0;
@@ -653,7 +721,9 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
             for (int a = 0; a < KB; ++a) acc[a][b] = mfma16x16x32bf16(abf[a], bbf, acc[a][b]);
           }
         }
-      }
+      };
+      const int st32 = m - c0 >= FCH ? FCH / 32 : (int)((m - c0 + 31) / 32);
+      for (int s32 = 0; s32 < st32; ++s32) gstep(s32);
     }
     gsync<C::NW>();
   }

@@ -586,7 +586,7 @@ __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64
     stage_store<PREC>(pre, smem, 0);
     __syncthreads();
     for (int ch = 0; ch < nch; ++ch) {
-      if (ch + 1 < nch) stage_load_clamped<PREC>(pre, xsrc, mp, n, q0, j0, ch + 1);
+      stage_load_clamped<PREC>(pre, xsrc, mp, n, q0, j0, ch + 1 < nch ? ch + 1 : ch);
       const float* base = As + (size_t)(ch & 1) * (KBQ + KBN) * G::ALD;
       const int h = lane / 32;
       float av[2][8], bv[8];
@@ -610,7 +610,7 @@ __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64
       for (int st = 0; st < 8; ++st)
 #pragma unroll
         for (int a = 0; a < 2; ++a) acc[a] = mfma32x32x2(av[a][st], bv[st], acc[a]);
-      if (ch + 1 < nch) stage_store<PREC>(pre, smem, (ch + 1) & 1);
+      stage_store<PREC>(pre, smem, (ch + 1) & 1);
       __syncthreads();
     }
     const int col = 32 * wc + lane % 32;
@@ -636,7 +636,7 @@ __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64
     stage_store<PREC>(pre, smem, 0);
     __syncthreads();
     for (int ch = 0; ch < nch; ++ch) {
-      if (ch + 1 < nch) stage_load_clamped<PREC>(pre, xsrc, mp, n, q0, j0, ch + 1);
+      stage_load_clamped<PREC>(pre, xsrc, mp, n, q0, j0, ch + 1 < nch ? ch + 1 : ch);
       const uint16_t* base = As + (size_t)(ch & 1) * (KBQ + KBN) * G::ALD;
 #pragma unroll
       for (int kk = 0; kk < 2; ++kk) {           // two 32-wide k steps per stage
@@ -654,7 +654,7 @@ __device__ __forceinline__ void tile_scores(const void* __restrict__ xsrc, int64
 #pragma unroll
           for (int b = 0; b < 2; ++b) acc[a][b] = mfma16x16x32bf16(av[a], bv[b], acc[a][b]);
       }
-      if (ch + 1 < nch) stage_store<PREC>(pre, smem, (ch + 1) & 1);
+      stage_store<PREC>(pre, smem, (ch + 1) & 1);
       __syncthreads();
     }
 #pragma unroll

@@ -679,9 +679,10 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
         for (int a = 0; a < KB; ++a)
           abf[a] = *reinterpret_cast<const shortx8*>(XB + (16 * a + lane % 16) * C::FLDB + col0);
         if constexpr (C::NW == 2 || C::NW == 4) {
-          // the operand rows of block b + 1 are read while block b's products are formed (with
-          // 8 waves per point the registers are kept for occupancy instead)
-          floatx4 pq[2][4];
+          // the operand rows of blocks b + 1 .. b + PD are in flight while block b's products
+          // are formed (depths 2 to 4 measured no faster than 1)
+          constexpr int PD = 1, RING = PD + 1;
+          floatx4 pq[RING][4];
           auto rd = [&](floatx4 (&d)[4], int b) {
             const ST* r1 = VS + off1[b] + col0;
             const ST* r2 = VS + off2[b] + col0;
@@ -690,11 +691,12 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
             d[2] = *reinterpret_cast<const floatx4*>(r2);
             d[3] = *reinterpret_cast<const floatx4*>(r2 + 4);
           };
-          rd(pq[0], 0);
+#pragma unroll
+          for (int b = 0; b < PD && b < C::NBW; ++b) rd(pq[b], b);
 #pragma unroll
           for (int b = 0; b < C::NBW; ++b) {
-            if (b + 1 < C::NBW) rd(pq[(b + 1) & 1], b + 1);
-            const floatx4(&cur)[4] = pq[b & 1];
+            if (b + PD < C::NBW) rd(pq[(b + PD) % RING], b + PD);
+            const floatx4(&cur)[4] = pq[b % RING];
             shortx8 bbf;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {

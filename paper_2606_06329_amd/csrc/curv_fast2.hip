@@ -394,17 +394,26 @@ struct RangeCfg {
   static constexpr int CPW = FCH / NW;
   static constexpr int RPG = (KMAX + NW - 1) / NW;          // patch rows per group
   static constexpr int VPG = 16 * KB / NW;                  // range rows per group (h)
+  // With several waves per point (float32 staging) the staged chunk (XS, XB) and its range
+  // rows (VS) are double buffered: chunk c + 1 is staged while other waves still read chunk c, so a chunk needs two
+  // barriers (staged; range rows formed).  h_c is formed from the V_r^T product's registers
+  // when every wave holds all range rows of its columns (NW divides FCH / 16).
+  static constexpr int NBUF = (NW > 1 && ESZ == 4) ? 2 : 1;   // float64 staging: 64 KiB cap
+  static constexpr bool HREG = (FCH / 16) % NW == 0;
+  static constexpr size_t XS_B = ((size_t)XROWS * FLDX * ESZ + 15) & ~(size_t)15;
+  static constexpr size_t VS_B = ((size_t)VROWS * FLDX * ESZ + 15) & ~(size_t)15;
   static constexpr size_t OFF_XS = 0;
-  static constexpr size_t OFF_VS = ((size_t)XROWS * FLDX * ESZ + 15) & ~(size_t)15;
-  static constexpr size_t OFF_RED = (OFF_VS + (size_t)VROWS * FLDX * ESZ + 15) & ~(size_t)15;
+  static constexpr size_t OFF_VS = NBUF * XS_B;
+  static constexpr size_t OFF_RED = OFF_VS + NBUF * VS_B;
   static constexpr size_t OFF_BJ = OFF_RED + (size_t)16 * NW * 8;          // tr G_j, r_j
   static constexpr size_t OFF_NB = OFF_BJ + (size_t)2 * KMAX * 8;
   static constexpr size_t OFF_PJ = OFF_NB + (size_t)KMAX * 4;
   // bf16 moments: the staged patch rows again as bf16, the A operand of the range GEMM
   // (rows of FLDB = 72 elements: 144 bytes, so 16 lanes' 16-byte reads hit distinct banks)
   static constexpr int FLDB = FCH + 8;
+  static constexpr size_t XB_B = BFA ? (((size_t)16 * KB * FLDB * 2 + 15) & ~(size_t)15) : 0;
   static constexpr size_t OFF_XB = (OFF_PJ + 2 * NPAD + 15) & ~(size_t)15;
-  static constexpr size_t BYTES = (OFF_XB + (BFA ? (size_t)16 * KB * FLDB * 2 : 0) + 15) & ~(size_t)15;
+  static constexpr size_t BYTES = OFF_XB + NBUF * XB_B;
 };
 
 template <int KMAX, int PREC>
@@ -444,14 +453,16 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
     return;
   }
   unsigned char* sm = smem_all + (size_t)gid * C::BYTES;
-  ST* XS = reinterpret_cast<ST*>(sm + C::OFF_XS);
-  ST* VS = reinterpret_cast<ST*>(sm + C::OFF_VS);
+  ST* XS0 = reinterpret_cast<ST*>(sm + C::OFF_XS);
+  ST* VS0 = reinterpret_cast<ST*>(sm + C::OFF_VS);
+  constexpr int XSE = (int)(C::XS_B / sizeof(ST)), VSE = (int)(C::VS_B / sizeof(ST));   // buffer strides
   double* RED = reinterpret_cast<double*>(sm + C::OFF_RED);
   double* BJ = reinterpret_cast<double*>(sm + C::OFF_BJ);
   int* nb = reinterpret_cast<int*>(sm + C::OFF_NB);
   unsigned char* pj1 = sm + C::OFF_PJ;
   unsigned char* pj2 = pj1 + C::NPAD;
-  uint16_t* XB = reinterpret_cast<uint16_t*>(sm + C::OFF_XB);
+  uint16_t* XB0 = reinterpret_cast<uint16_t*>(sm + C::OFF_XB);
+  constexpr int XBE = (int)(C::XB_B / 2);
   const int pe = reinterpret_cast<const int*>(ws + L.off_pe)[i];
   const double tauk = reinterpret_cast<const double*>(ws + L.off_tau)[i];
   const double tS = reinterpret_cast<const double*>(ws + L.off_ts)[i];
@@ -478,10 +489,13 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
     pj1[t] = (unsigned char)a;
     pj2[t] = (unsigned char)b;
   }
-  for (int t = tg; t < (16 * KB - k) * FLDX; t += C::NTG) XS[k * FLDX + t] = (ST)0;
-  if constexpr (PREC == MOM_BF16)
-    for (int t = tg; t < (16 * KB - k) * C::FLDB; t += C::NTG) XB[k * C::FLDB + t] = 0;
-  for (int t = tg; t < FLDX; t += C::NTG) VS[C::VZERO * FLDX + t] = (ST)0;
+#pragma unroll
+  for (int bf = 0; bf < C::NBUF; ++bf) {
+    for (int t = tg; t < (16 * KB - k) * FLDX; t += C::NTG) XS0[bf * XSE + k * FLDX + t] = (ST)0;
+    if constexpr (PREC == MOM_BF16)
+      for (int t = tg; t < (16 * KB - k) * C::FLDB; t += C::NTG) XB0[bf * XBE + k * C::FLDB + t] = 0;
+    for (int t = tg; t < FLDX; t += C::NTG) VS0[bf * VSE + C::VZERO * FLDX + t] = (ST)0;
+  }
   // Ut^T operand of the V_r^T chunk product: A[l][j] = Ut[j][l] at row l = 16 lb + lane%16,
   // k index j = 16 jb + st + 4 (lane/16): the four lane groups read patch rows four apart,
   // 16 banks apart in LDS, so the B operand's reads are conflict-free
@@ -516,6 +530,9 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
     const int j = grp * C::RPG + r;
     nbr_[r] = j < k ? nb[j] : 0;
   }
+  ST* XS = XS0;          // the current chunk's buffers (the lambdas below read these)
+  ST* VS = VS0;
+  uint16_t* XB = XB0;
   float xr[C::RPG];
   auto load = [&](int64_t c0) {
     const int64_t c = c0 + colw;
@@ -592,11 +609,20 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
     for (int b = 0; b < C::NBW; ++b) acc[a][b] = AccT{0, 0, 0, 0};
   double tD = 0.0;
   load(0);
+  int buf = 0;
   for (int64_t c0 = 0; c0 < m; c0 += FCH) {
+    XS = XS0 + buf * XSE;
+    VS = VS0 + buf * VSE;
+    XB = XB0 + buf * XBE;
+    if constexpr (C::NBUF == 2) buf ^= 1;
     stage(c0);
     gsync<C::NW>();
     if (c0 + FCH < m) load(c0 + FCH);
-    // V_r^T chunk = Ut^T X_c (rows l, columns c of the chunk)
+    // V_r^T chunk = Ut^T X_c (rows l, columns c of the chunk); with HREG each wave also sums
+    // h over the rows it formed, for its columns 16 cb .. 16 cb + 15
+    ST hsum[C::VBW];
+#pragma unroll
+    for (int t = 0; t < C::VBW; ++t) hsum[t] = 0;
 #pragma unroll
     for (int t = 0; t < C::VBW; ++t) {
       const int vb = w + C::NW * t;
@@ -614,13 +640,37 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int l = 16 * lb + (PREC == MOM_FP64 ? lane / 16 + 4 * r : 4 * (lane / 16) + r);
-          VS[l * FLDX + 16 * cb + lane % 16] = (ST)v[r];
+          const ST vr = (ST)v[r];
+          VS[l * FLDX + 16 * cb + lane % 16] = vr;
+          hsum[t] += vr * vr;
+        }
+      }
+    }
+    if constexpr (C::HREG) {
+      // wave w's blocks t cover column block cb = (w + NW t) % (FCH / 16) for every row block:
+      // h_c (rows l >= pe hold zeros), the ones row and t_D's sum_c q_c h_c without a barrier
+#pragma unroll
+      for (int t = 0; t < C::VBW; ++t) {
+        const int vb = w + C::NW * t;
+        if (vb < FCH / 16) {          // the first row block of each of the wave's columns
+          ST h = 0;
+#pragma unroll
+          for (int t2 = 0; t2 < C::VBW; ++t2)
+            if ((w + C::NW * t2) % (FCH / 16) == vb) h += hsum[t2];
+          h += __shfl_xor(h, 16, WAVE);
+          h += __shfl_xor(h, 32, WAVE);
+          if (lane < 16) {
+            const int col = 16 * vb + lane;
+            VS[C::VH * FLDX + col] = h;
+            VS[C::VONE * FLDX + col] = (c0 + col < m) ? (ST)1 : (ST)0;
+            tD = fma((double)XS[C::XQ * FLDX + col], (double)h, tD);
+          }
         }
       }
     }
     gsync<C::NW>();
     // h_c = sum_l V[c, l]^2 (rows l >= pe hold zeros), the ones row, and t_D's sum_c q_c h_c
-    {
+    if constexpr (!C::HREG) {
       ST h = 0;
 #pragma unroll
       for (int r = 0; r < C::VPG; ++r) {
@@ -634,8 +684,8 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
         VS[C::VONE * FLDX + colw] = (c0 + colw < m) ? (ST)1 : (ST)0;
         tD = fma((double)XS[C::XQ * FLDX + colw], (double)h, tD);
       }
+      gsync<C::NW>();
     }
-    gsync<C::NW>();
     if constexpr (PREC == MOM_FP64) {
       const int st4 = m - c0 >= FCH ? FCH / 4 : (int)((m - c0 + 3) / 4);
       for (int s4 = 0; s4 < st4; ++s4) {
@@ -727,8 +777,10 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
       const int st32 = m - c0 >= FCH ? FCH / 32 : (int)((m - c0 + 31) / 32);
       for (int s32 = 0; s32 < st32; ++s32) gstep(s32);
     }
-    gsync<C::NW>();
+    // single buffers: the next chunk's staging overwrites what this GEMM reads
+    if constexpr (C::NBUF == 1) gsync<C::NW>();
   }
+  gsync<C::NW>();
 
   // ---- reductions: raw sums (k-1) * (t_range, g, t_A, t_S, t_D) ------------------------
   double part[5] = {0.0, 0.0, 0.0, 0.0, tD};

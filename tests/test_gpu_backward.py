@@ -187,3 +187,26 @@ def test_autograd_function():
         P.curvature_backward(Xd.detach(), idx, w[:10], "haar")
     with pytest.raises(ValueError):
         P.curvature_backward(Xd.detach(), idx, w.cpu(), "haar")
+
+
+def test_backward_run_to_run():
+    """The scatter-add into grad_X uses float32 atomics, so the order of each entry's sum, and
+    its last bits, vary between runs; the per-point terms themselves are deterministic.  Two
+    runs on the same inputs may therefore differ by at most the rounding of two orders of the
+    same sum: 2 (N - 1) 2^-24 sum |c| for an entry of N terms (N = the number of patches that
+    contain the row), with sum |c| bounded by the oracle's contribution scale."""
+    n, m, k = 2000, 16, 8
+    X = synth.WORKLOADS["swissroll"][0](n=n, m=m, seed=97)
+    idx, _, _, _ = ok.knn(X.astype(np.float64), k)
+    w = synth.loss_weights(n, seed=97)
+    print(f"backward run to run, swissroll n={n} m={m} k={k}", flush=True)
+    g1, _, _ = _gpu_grad(X, idx, w, "paper")
+    g2, _, _ = _gpu_grad(X, idx, w, "paper")
+    S = oa.grad_contribution_scale(X.astype(np.float64), idx, w.astype(np.float64), "paper")
+    terms = np.bincount(idx.ravel(), minlength=n).astype(np.float64)
+    bound = 2.0 * np.maximum(terms - 1.0, 0.0)[:, None] * 2.0 ** -24 * 1.01 * S
+    diff = np.abs(g1 - g2)
+    print(f"  entries that differ: {int((diff > 0).sum())} of {diff.size}, "
+          f"max diff / bound {np.max(np.where(bound > 0, diff / np.maximum(bound, 1e-300), 0.0)):.3f}",
+          flush=True)
+    assert np.all(diff <= bound)

@@ -261,13 +261,22 @@ __device__ int jacobi_sweeps(const PointLds& P, JT* JA, JT* JV, int k, int tg, J
       if constexpr (C::NW > 1) rot = misc[3 + (r & 1)];
       if (!rot) continue;                 // nothing rotates in this round
       swept = 1;
-      // A <- J^T A J on 2 x 2 blocks
+      // A <- J^T A J on 2 x 2 blocks.  When the thread count is a multiple of HP, a thread's
+      // column block bj is the same for all its blocks: its plane and rotation are read once.
+      constexpr bool FIXJ = C::NTG % HP == 0;
+      int pqj = 0;
+      JT cj = 0, sj = 0;
+      if constexpr (FIXJ) {
+        pqj = pr[tg % HP];
+        cj = ROT[tg % HP];
+        sj = ROT[C::KK / 2 + tg % HP];
+      }
       for (int u = tg; u < HP * HP; u += C::NTG) {
         const int bi = u / HP, bj = u % HP;
-        const int pq1 = pr[bi], pq2 = pr[bj];
+        const int pq1 = pr[bi], pq2 = FIXJ ? pqj : pr[bj];
         const int p = pq1 & 0xff, q = pq1 >> 8, p2 = pq2 & 0xff, q2 = pq2 >> 8;
         const JT c = ROT[bi], sn = ROT[C::KK / 2 + bi];
-        const JT c2 = ROT[bj], s2 = ROT[C::KK / 2 + bj];
+        const JT c2 = FIXJ ? cj : ROT[bj], s2 = FIXJ ? sj : ROT[C::KK / 2 + bj];
         const JT a00 = JA[p * C::JLD + p2], a01 = JA[p * C::JLD + q2];
         const JT a10 = JA[q * C::JLD + p2], a11 = JA[q * C::JLD + q2];
         // columns: (p2, q2) <- (c2 a_p2 - s2 a_q2, s2 a_p2 + c2 a_q2)
@@ -289,9 +298,9 @@ __device__ int jacobi_sweeps(const PointLds& P, JT* JA, JT* JV, int k, int tg, J
       for (int u = tg; u < KK * HP; u += C::NTG) {
         const int x = u / HP, bj = u % HP;
         if (x < k) {
-          const int pq2 = pr[bj];
+          const int pq2 = FIXJ ? pqj : pr[bj];
           const int p2 = pq2 & 0xff, q2 = pq2 >> 8;
-          const JT c2 = ROT[bj], s2 = ROT[C::KK / 2 + bj];
+          const JT c2 = FIXJ ? cj : ROT[bj], s2 = FIXJ ? sj : ROT[C::KK / 2 + bj];
           const JT v0 = JV[x * C::JLD + p2], v1 = JV[x * C::JLD + q2];
           JV[x * C::JLD + p2] = c2 * v0 - s2 * v1;
           JV[x * C::JLD + q2] = s2 * v0 + c2 * v1;

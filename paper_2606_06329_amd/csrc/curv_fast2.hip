@@ -385,7 +385,11 @@ struct RangeCfg {
   static constexpr int NB = (NCOLMAX + 15) / 16;
   static constexpr int NPAD = NB * 16;
   static constexpr int NBW = (NB + NW - 1) / NW;            // column blocks per wave
-  static constexpr int XQ = 16 * KB, XONE = 16 * KB + 1, XROWS = 16 * KB + 2;   // patch chunk rows
+  // bf16 moments with several waves per point form V_r^T from bf16 high/low parts (VBF)
+  static constexpr bool VBF = BFA && NW_ > 1;
+  // patch chunk rows: the centred rows, q and ones (with VBF only q and ones stay in XS: the
+  // patch goes to XB and, transposed and split into bf16 high and low parts, to XT)
+  static constexpr int XQ = VBF ? 0 : 16 * KB, XONE = XQ + 1, XROWS = XQ + 2;
   static constexpr int VH = 16 * KB, VONE = 16 * KB + 1, VZERO = 16 * KB + 2;   // range chunk rows
   static constexpr int VROWS = 16 * KB + 3;
   static constexpr int VBLK = KB * (FCH / 16);              // blocks of the V_r^T chunk product
@@ -413,7 +417,12 @@ struct RangeCfg {
   static constexpr int FLDB = FCH + 8;
   static constexpr size_t XB_B = BFA ? (((size_t)16 * KB * FLDB * 2 + 15) & ~(size_t)15) : 0;
   static constexpr size_t OFF_XB = (OFF_PJ + 2 * NPAD + 15) & ~(size_t)15;
-  static constexpr size_t BYTES = OFF_XB + NBUF * XB_B;
+  // XT[c][j] (high part, then low part): the B operand of the bf16 V_r^T product, K = j; rows of
+  // FLDT = 40 elements (80 bytes: 16 lanes' 16-byte reads hit distinct banks)
+  static constexpr int FLDT = 40;
+  static constexpr size_t XT_B = VBF ? (size_t)2 * FCH * FLDT * 2 : 0;
+  static constexpr size_t OFF_XT = OFF_XB + NBUF * XB_B;
+  static constexpr size_t BYTES = OFF_XT + NBUF * XT_B;
 };
 
 template <int KMAX, int PREC>
@@ -463,6 +472,8 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
   unsigned char* pj2 = pj1 + C::NPAD;
   uint16_t* XB0 = reinterpret_cast<uint16_t*>(sm + C::OFF_XB);
   constexpr int XBE = (int)(C::XB_B / 2);
+  uint16_t* XT0 = reinterpret_cast<uint16_t*>(sm + C::OFF_XT);
+  constexpr int XTE = (int)(C::XT_B / 2), XTLO = FCH * C::FLDT;   // buffer stride, low-part offset
   const int pe = reinterpret_cast<const int*>(ws + L.off_pe)[i];
   const double tauk = reinterpret_cast<const double*>(ws + L.off_tau)[i];
   const double tS = reinterpret_cast<const double*>(ws + L.off_ts)[i];
@@ -491,24 +502,48 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
   }
 #pragma unroll
   for (int bf = 0; bf < C::NBUF; ++bf) {
-    for (int t = tg; t < (16 * KB - k) * FLDX; t += C::NTG) XS0[bf * XSE + k * FLDX + t] = (ST)0;
+    if constexpr (!C::VBF)
+      for (int t = tg; t < (16 * KB - k) * FLDX; t += C::NTG) XS0[bf * XSE + k * FLDX + t] = (ST)0;
     if constexpr (PREC == MOM_BF16)
       for (int t = tg; t < (16 * KB - k) * C::FLDB; t += C::NTG) XB0[bf * XBE + k * C::FLDB + t] = 0;
+    if constexpr (C::VBF) {
+      for (int t = tg; t < 2 * FCH * (32 - k); t += C::NTG) {   // XT entries j >= k, both parts
+        const int pl = t / (FCH * (32 - k)), r = t % (FCH * (32 - k));
+        XT0[bf * XTE + pl * XTLO + (r / (32 - k)) * C::FLDT + k + r % (32 - k)] = 0;
+      }
+    }
     for (int t = tg; t < FLDX; t += C::NTG) VS0[bf * VSE + C::VZERO * FLDX + t] = (ST)0;
   }
   // Ut^T operand of the V_r^T chunk product: A[l][j] = Ut[j][l] at row l = 16 lb + lane%16,
   // k index j = 16 jb + st + 4 (lane/16): the four lane groups read patch rows four apart,
   // 16 banks apart in LDS, so the B operand's reads are conflict-free
-  ST ua[KB][KB][4];
+  constexpr int UAK = C::VBF ? 1 : KB;
+  ST ua[KB][UAK][4];
+  // VBF: Ut^T split into bf16 high and low parts, A[l][j] with k index j = 8 (lane/16) + e of
+  // one 16x16x32 step (k <= 32)
+  shortx8 uah[KB], ual[KB];
+  if constexpr (C::VBF) {
 #pragma unroll
-  for (int lb = 0; lb < KB; ++lb)
+    for (int lb = 0; lb < KB; ++lb)
 #pragma unroll
-    for (int jb = 0; jb < KB; ++jb)
-#pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        const int l = 16 * lb + lane % 16, j = 16 * jb + st + 4 * (lane / 16);
-        ua[lb][jb][st] = (l < pe && j < k) ? UT[j * KMAX + l] : (ST)0;
+      for (int e = 0; e < 8; ++e) {
+        const int l = 16 * lb + lane % 16, j = 8 * (lane / 16) + e;
+        const float u = (l < pe && j < k) ? (float)UT[j * KMAX + l] : 0.0f;
+        const uint16_t hi = f2bf(u);
+        uah[lb][e] = (short)hi;
+        ual[lb][e] = (short)f2bf(u - __uint_as_float((uint32_t)hi << 16));
       }
+  } else {
+#pragma unroll
+    for (int lb = 0; lb < KB; ++lb)
+#pragma unroll
+      for (int jb = 0; jb < KB; ++jb)
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int l = 16 * lb + lane % 16, j = 16 * jb + st + 4 * (lane / 16);
+          ua[lb][jb][st] = (l < pe && j < k) ? UT[j * KMAX + l] : (ST)0;
+        }
+  }
   gsync<C::NW>();
   // column blocks past the point's ncol columns read the zero row, so every wave runs all NBW
   // blocks without a branch and the compiler can interleave their loads
@@ -533,6 +568,7 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
   ST* XS = XS0;          // the current chunk's buffers (the lambdas below read these)
   ST* VS = VS0;
   uint16_t* XB = XB0;
+  uint16_t* XT = XT0;
   float xr[C::RPG];
   auto load = [&](int64_t c0) {
     const int64_t c = c0 + colw;
@@ -591,8 +627,15 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
         if (j < k) {
           const float xc = d[r] - mean;
           q = fmaf(xc, xc, q);
-          XS[j * FLDX + colw] = xc;
-          if constexpr (PREC == MOM_BF16) XB[j * C::FLDB + colw] = f2bf(xc);
+          if constexpr (C::VBF) {
+            const uint16_t hi = f2bf(xc);
+            XB[j * C::FLDB + colw] = hi;
+            XT[colw * C::FLDT + j] = hi;
+            XT[XTLO + colw * C::FLDT + j] = f2bf(xc - __uint_as_float((uint32_t)hi << 16));
+          } else {
+            XS[j * FLDX + colw] = xc;
+            if constexpr (PREC == MOM_BF16) XB[j * C::FLDB + colw] = f2bf(xc);
+          }
         }
       }
 #pragma unroll
@@ -614,6 +657,7 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
     XS = XS0 + buf * XSE;
     VS = VS0 + buf * VSE;
     XB = XB0 + buf * XBE;
+    XT = XT0 + buf * XTE;
     if constexpr (C::NBUF == 2) buf ^= 1;
     stage(c0);
     gsync<C::NW>();
@@ -629,14 +673,25 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
       if (vb < C::VBLK) {
         const int lb = vb / (FCH / 16), cb = vb % (FCH / 16);
         AccT v = AccT{0, 0, 0, 0};
+        if constexpr (C::VBF) {
+          // three bf16 products (high x low, low x high, high x high, the small terms first):
+          // Ut^T X_c to about 2^-16 of the terms, far inside the bf16 range products' 2^-9
+          const uint16_t* xt = XT + (16 * cb + lane % 16) * C::FLDT + 8 * (lane / 16);
+          const shortx8 xh = *reinterpret_cast<const shortx8*>(xt);
+          const shortx8 xl = *reinterpret_cast<const shortx8*>(xt + XTLO);
+          v = mfma16x16x32bf16(uah[lb], xl, v);
+          v = mfma16x16x32bf16(ual[lb], xh, v);
+          v = mfma16x16x32bf16(uah[lb], xh, v);
+        } else {
 #pragma unroll
-        for (int jb = 0; jb < KB; ++jb)
+          for (int jb = 0; jb < KB; ++jb)
 #pragma unroll
-          for (int st = 0; st < 4; ++st) {
-            const ST bv = XS[(16 * jb + st + 4 * (lane / 16)) * FLDX + 16 * cb + lane % 16];
-            if constexpr (PREC == MOM_FP64) v = mfma16x16x4f64(ua[lb][jb][st], bv, v);
-            else v = mfma16x16x4(ua[lb][jb][st], bv, v);
-          }
+            for (int st = 0; st < 4; ++st) {
+              const ST bv = XS[(16 * jb + st + 4 * (lane / 16)) * FLDX + 16 * cb + lane % 16];
+              if constexpr (PREC == MOM_FP64) v = mfma16x16x4f64(ua[lb][jb][st], bv, v);
+              else v = mfma16x16x4(ua[lb][jb][st], bv, v);
+            }
+        }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int l = 16 * lb + (PREC == MOM_FP64 ? lane / 16 + 4 * r : 4 * (lane / 16) + r);

@@ -621,6 +621,10 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
       for (int o = C::CPW; o < WAVE; o <<= 1) s += __shfl_xor(s, o, WAVE);
       const float mean = s / (float)k;
       float q = 0.0f;
+      // with eight rows per group the transposed high and low parts of the group's rows are
+      // eight consecutive entries of XT: one 16-byte store each (zeros past row k)
+      constexpr bool XT8 = C::VBF && C::RPG == 8;
+      shortx8 th = {0, 0, 0, 0, 0, 0, 0, 0}, tl = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
       for (int r = 0; r < C::RPG; ++r) {
         const int j = grp * C::RPG + r;
@@ -629,14 +633,24 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
           q = fmaf(xc, xc, q);
           if constexpr (C::VBF) {
             const uint16_t hi = f2bf(xc);
+            const uint16_t lo = f2bf(xc - __uint_as_float((uint32_t)hi << 16));
             XB[j * C::FLDB + colw] = hi;
-            XT[colw * C::FLDT + j] = hi;
-            XT[XTLO + colw * C::FLDT + j] = f2bf(xc - __uint_as_float((uint32_t)hi << 16));
+            if constexpr (XT8) {
+              th[r % 8] = (short)hi;
+              tl[r % 8] = (short)lo;
+            } else {
+              XT[colw * C::FLDT + j] = hi;
+              XT[XTLO + colw * C::FLDT + j] = lo;
+            }
           } else {
             XS[j * FLDX + colw] = xc;
             if constexpr (PREC == MOM_BF16) XB[j * C::FLDB + colw] = f2bf(xc);
           }
         }
+      }
+      if constexpr (XT8) {
+        *reinterpret_cast<shortx8*>(XT + colw * C::FLDT + 8 * grp) = th;
+        *reinterpret_cast<shortx8*>(XT + XTLO + colw * C::FLDT + 8 * grp) = tl;
       }
 #pragma unroll
       for (int o = C::CPW; o < WAVE; o <<= 1) q += __shfl_xor(q, o, WAVE);

@@ -192,10 +192,10 @@ def roofline(P, stages, n, m, k, prec, workload):
     """Roofline entry of the kernel with the largest average launch time among those with a
     stated algorithmic work: the distance GEMM (n (n+1) m flop under the symmetric tile-pair
     schedule, 2 n^2 m otherwise, at its precision's MFMA peak), the range pass of the two-pass
-    Fast form (per point 2 k (k-1) m float32 MFMA flop for V_r^T = Ut^T X_c and
-    2 k m ((k-1) k / 2 + 2) flop for the G_tens / trace / row-sum GEMM at the moment
-    precision's peak; the peak reported is the work over its shortest possible time) and the
-    Gram pass (k (k+1) m float32 MFMA flop per point)."""
+    Fast form (per point 2 k (k-1) m flop for V_r^T = Ut^T X_c and 2 k m ((k-1) k / 2 + 2) flop
+    for the G_tens / trace / row-sum GEMM, each at the peak of the MFMA it runs on; the peak
+    reported is the work over its shortest possible time) and the Gram pass (k (k+1) m float32
+    MFMA flop per point)."""
     kprec, cprec, _ = PRECISIONS[prec]
     cand = {}
     if "knn_gemm_topk" in stages:
@@ -209,10 +209,13 @@ def roofline(P, stages, n, m, k, prec, workload):
         fv = 2.0 * k * p * m * n
         fg = 2.0 * k * m * (p * k / 2 + 2) * n
         gp = PEAK["fp32" if cprec == "fp32" else ("fp64" if cprec == "fp64" else "bf16")]
-        vp = PEAK["fp64" if cprec == "fp64" else "fp32"]
+        # the V_r^T product: float32 MFMA, float64 for float64 moments, and bf16 MFMA (high/low
+        # parts) on the bf16 path with several waves per point (k > 16)
+        vprec = "fp64" if cprec == "fp64" else ("bf16" if cprec == "bf16" and k > 16 else "fp32")
+        vp = PEAK[vprec]
         tmin = fv / (vp * 1e12) + fg / (gp * 1e12)
         cand["curv_range"] = (fv + fg, tmin,
-                              f"per point 2k(k-1)m = {fv / n:.4g} flop ({'fp64' if cprec == 'fp64' else 'fp32'} MFMA) "
+                              f"per point 2k(k-1)m = {fv / n:.4g} flop ({vprec} MFMA) "
                               f"+ 2km((k-1)k/2+2) = {fg / n:.4g} flop ({cprec} MFMA), x n = {fv + fg:.4g} per launch")
     if "curv_gram" in stages:
         f = float(k) * (k + 1) * m * n

@@ -19,7 +19,8 @@ int check_cloud(const float* X, int64_t n, int64_t m, int64_t ldx, int32_t k) {
   if (n <= 0 || m <= 0 || ldx < m) return MC_EINVAL;
   if (k < 2 || k > MC_KMAX || (int64_t)k >= n) return MC_EINVAL;
   if (n > kIdxMax) return MC_ESHAPE;
-  if (n * ldx / ldx != n) return MC_ESHAPE;
+  int64_t elems = 0;
+  if (__builtin_mul_overflow(n, ldx, &elems)) return MC_ESHAPE;   // n x ldx floats addressable
   return MC_OK;
 }
 
@@ -71,6 +72,8 @@ size_t mc_workspace_bytes(int32_t op, int64_t n, int64_t m, int32_t k, int32_t p
                           int32_t rerank_factor) {
   if (op == MC_OP_NORMALIZE) return n > 0 ? mc::normalize_ws_bytes() : 0;
   if (n <= 0 || m <= 0 || k < 2 || k > MC_KMAX || (int64_t)k >= n) return 0;
+  int64_t elems = 0;   // the calls reject these shapes (ldx >= m, so n x ldx would overflow too)
+  if (n > kIdxMax || __builtin_mul_overflow(n, m, &elems)) return 0;
   switch (op) {
     case MC_OP_KNN: {
       if (precision != MC_FP32 && precision != MC_BF16 && precision != MC_FP8) return 0;

@@ -1261,7 +1261,7 @@ __global__ __launch_bounds__(256) void knn_collect_kernel(const float* __restric
   const int64_t PB = b_pairs(S), P = PB + S.T;
   const int64_t L = blockIdx.x;
   const int64_t tb = (L * P) / G, te = ((L + 1) * P) / G;
-  __shared__ float q_thr[2][KBQ], q_T[2][KBQ], q_a[2][KBQ], q_n[2][KBQ], q_e[2][KBQ];
+  __shared__ __align__(16) float q_thr[2][KBQ], q_T[2][KBQ], q_a[2][KBQ], q_n[2][KBQ], q_e[2][KBQ];
   const int tid = threadIdx.x;
   const double u = 0x1p-24;
   for (int64_t t = tb; t < te; ++t) {
@@ -1292,8 +1292,9 @@ __global__ __launch_bounds__(256) void knn_collect_kernel(const float* __restric
     __syncthreads();
     const float* tile = tbuf + t * (int64_t)(KBQ * KBN);
     // pass v: thread tid reads the 16 bytes at float4 index tid + 256 v (row c, columns r..r+3),
-    // so every load instruction of a wave covers 1 KiB of consecutive memory
-#pragma unroll 4
+    // so every load instruction of a wave covers 1 KiB of consecutive memory; eight passes are
+    // in flight at a time
+#pragma unroll 8
     for (int v = 0; v < KBQ * KBN / (4 * 256); ++v) {
       const int f = tid + 256 * v;
       const int c = f / (KBN / 4), rb = 4 * (f % (KBN / 4));
@@ -1302,6 +1303,11 @@ __global__ __launch_bounds__(256) void knn_collect_kernel(const float* __restric
       const int64_t qc = ct * KBQ + c;
       const float thc = q_thr[0][c];
       const float nc = q_n[0][c], ec = q_e[0][c];
+      // the four row queries' thresholds and norms: one 16-byte LDS read each
+      const float4 thr4 = *reinterpret_cast<const float4*>(&q_thr[1][rb]);
+      const float4 nr4 = *reinterpret_cast<const float4*>(&q_n[1][rb]);
+      const float thrv[4] = {thr4.x, thr4.y, thr4.z, thr4.w};
+      const float nrv[4] = {nr4.x, nr4.y, nr4.z, nr4.w};
 #pragma unroll
       for (int e4 = 0; e4 < 4; ++e4) {
         const int r = rb + e4;
@@ -1317,9 +1323,9 @@ __global__ __launch_bounds__(256) void knn_collect_kernel(const float* __restric
         }
         // candidate c for query r (off-diagonal tiles): re-associate the stored score
         if (t < PB && qr < n && qc < n) {
-          const float thr = q_thr[1][r];
+          const float thr = thrv[e4];
           if (thr > -INFINITY) {
-            const float s2 = (s - q_n[1][r]) + nc;
+            const float s2 = (s - nrv[e4]) + nc;
             if (s2 <= thr) {
               const float lb = sqrtf(fmaxf(0.0f, s2 + q_a[1][r])) * (1.0f - 0x1p-22f) - ec;
               if (lb <= q_T[1][r]) {

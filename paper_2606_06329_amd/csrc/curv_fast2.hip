@@ -60,6 +60,44 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Lane exchanges across 16-lane rows without the LDS crossbar (gfx950 permlane swaps):
+// permlane16_swap(v, v) yields, in every lane, the values of its row pair in row order, and
+// permlane32_swap(v, v) those of its half pair; their sum is the xor-16 (xor-32) butterfly sum,
+// the same in both lanes of a pair (the two addends in a fixed order).
+__device__ __forceinline__ float xsum16(float x) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float xsum32(float x) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+// sum over the lanes l' with l' % CPW == l % CPW (CPW = 64 / number of lane groups)
+template <int CPW>
+__device__ __forceinline__ float group_sum_f(float x) {
+#pragma unroll
+  for (int o = CPW; o < 16 && o < WAVE; o <<= 1) x += __shfl_xor(x, o, WAVE);
+  if constexpr (CPW <= 16) x = xsum16(x);
+  if constexpr (CPW <= 32) x = xsum32(x);
+  return x;
+}
+// the value of lane l % CPW in every lane (row 0's copy of each column)
+template <int CPW>
+__device__ __forceinline__ float group_bcast_f(float x) {
+  if constexpr (CPW == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    const auto t = __builtin_amdgcn_permlane32_swap(r[0], r[0], false, false);
+    return __uint_as_float(t[0]);
+  } else if constexpr (CPW == 32) {
+    const auto t = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(t[0]);
+  } else if constexpr (CPW == WAVE) {
+    return x;
+  } else {
+    return __shfl(x, lane_id() % CPW, WAVE);
+  }
+}
+
 // ---- 1. Gram pass: one wave per point, four points per workgroup ------------------------
 template <int KMAX, int PREC>
 struct GramCfg {
@@ -608,7 +646,7 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
       for (int o = C::CPW; o < WAVE; o <<= 1) q += __shfl_xor(q, o, WAVE);
       if (grp == 0) XS[C::XQ * FLDX + colw] = q;
     } else {
-      const float x0 = __shfl(xr[0], cl, WAVE);
+      const float x0 = group_bcast_f<C::CPW>(xr[0]);
       float d[C::RPG];
       float s = 0.0f;
 #pragma unroll
@@ -617,8 +655,7 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
         d[r] = j < k ? xr[r] - x0 : 0.0f;
         s += d[r];
       }
-#pragma unroll
-      for (int o = C::CPW; o < WAVE; o <<= 1) s += __shfl_xor(s, o, WAVE);
+      s = group_sum_f<C::CPW>(s);
       const float mean = s / (float)k;
       float q = 0.0f;
       // with eight rows per group the transposed high and low parts of the group's rows are
@@ -652,8 +689,7 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
         *reinterpret_cast<shortx8*>(XT + colw * C::FLDT + 8 * grp) = th;
         *reinterpret_cast<shortx8*>(XT + XTLO + colw * C::FLDT + 8 * grp) = tl;
       }
-#pragma unroll
-      for (int o = C::CPW; o < WAVE; o <<= 1) q += __shfl_xor(q, o, WAVE);
+      q = group_sum_f<C::CPW>(q);
       if (grp == 0) XS[C::XQ * FLDX + colw] = q;
     }
     if (grp == 0) XS[C::XONE * FLDX + colw] = (c0 + colw < m) ? (ST)1 : (ST)0;
@@ -726,8 +762,12 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
 #pragma unroll
           for (int t2 = 0; t2 < C::VBW; ++t2)
             if ((w + C::NW * t2) % (FCH / 16) == vb) h += hsum[t2];
-          h += __shfl_xor(h, 16, WAVE);
-          h += __shfl_xor(h, 32, WAVE);
+          if constexpr (PREC == MOM_FP64) {
+            h += __shfl_xor(h, 16, WAVE);
+            h += __shfl_xor(h, 32, WAVE);
+          } else {
+            h = xsum32(xsum16(h));
+          }
           if (lane < 16) {
             const int col = 16 * vb + lane;
             VS[C::VH * FLDX + col] = h;

@@ -6,7 +6,8 @@ top-K' + float32 re-rank + certificate, and the rescan of uncertified queries)
 followed by mc_curvature_fast (Fast branch of Algorithm 1), inputs resident in
 HBM.  The headline workload is the largest configuration, the 50000 x 4096 blob
 mixture with k = 32: fp8 e4m3 distance GEMM with per-row scales and a float32
-re-rank of 64 candidates, bf16 range products with float32 Gram and eigen-solve.
+re-rank of 64 candidates, Gram from split bf16 products (x = hi + lo), float32
+eigen-solve, bf16 range products.
 
 Prints ONE JSON line with the metric, a roofline entry for the dominant kernel
 (timed with the library's hipEvent stage timers on the launch stream), the
@@ -194,8 +195,9 @@ def roofline(P, stages, n, m, k, prec, workload):
     schedule, 2 n^2 m otherwise, at its precision's MFMA peak), the range pass of the two-pass
     Fast form (per point 2 k (k-1) m flop for V_r^T = Ut^T X_c and 2 k m ((k-1) k / 2 + 2) flop
     for the G_tens / trace / row-sum GEMM, each at the peak of the MFMA it runs on; the peak
-    reported is the work over its shortest possible time) and the Gram pass (k (k+1) m float32
-    MFMA flop per point)."""
+    reported is the work over its shortest possible time) and the Gram pass (k (k+1) m flop per
+    point at the peak of its MFMA: float32, float64 for float64 moments, bf16 for the split bf16
+    products of the bf16 path)."""
     kprec, cprec, _ = PRECISIONS[prec]
     cand = {}
     if "knn_gemm_topk" in stages:
@@ -219,9 +221,9 @@ def roofline(P, stages, n, m, k, prec, workload):
                               f"+ 2km((k-1)k/2+2) = {fg / n:.4g} flop ({cprec} MFMA), x n = {fv + fg:.4g} per launch")
     if "curv_gram" in stages:
         f = float(k) * (k + 1) * m * n
-        cand["curv_gram"] = (f, f / (PEAK["fp64" if cprec == "fp64" else "fp32"] * 1e12),
-                             f"k(k+1)m per point x n = {f:.4g} flop per launch, "
-                             f"{'fp64' if cprec == 'fp64' else 'fp32'} MFMA")
+        gprec = cprec if cprec in ("fp64", "bf16") else "fp32"
+        cand["curv_gram"] = (f, f / (PEAK[gprec] * 1e12),
+                             f"k(k+1)m per point x n = {f:.4g} flop per launch, {gprec} MFMA")
     if not cand:
         return None
     name = max(cand, key=lambda s: stages[s][0] / stages[s][1])

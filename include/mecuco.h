@@ -151,10 +151,11 @@ int mc_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int32_t k, int32_t
  *                float32 moments lose digits.  k > MC_FAST_FP64_KMAX -> MC_ESHAPE.
  *                A point is flagged MC_PF_PRECISION_LIMIT when 2 u cond / max(q, 1) exceeds
  *                the path's error budget, with cond = sigma_1 / sigma_pe of the Gram matrix,
- *                q = m - pe, u = 2^-24 for MC_FP32 and MC_BF16 (float32 Gram), 2^-53 for
- *                MC_FP64, and budgets 1e-4, 2e-2 and 1e-6: the moments' rounding turns the
- *                weakest kept direction by about u cond towards the null space, whose term
- *                spreads that over its q directions.
+ *                q = m - pe, u = 2^-24 for MC_FP32 and for MC_BF16 at k <= 12 (float32
+ *                Gram), 3 * 2^-16 for MC_BF16 at k >= 13 (Gram from split bf16 products,
+ *                x = hi + lo), 2^-53 for MC_FP64, and budgets 1e-4, 2e-2 and 1e-6: the
+ *                moments' rounding turns the weakest kept direction by about u cond
+ *                towards the null space, whose term spreads that over its q directions.
  *                MC_BF16 moments on rows narrower than 256 flag every point
  *                MC_PF_PRECISION_LIMIT (their 8-bit products exceed the 2e-2 budget on
  *                strongly curved patches there)

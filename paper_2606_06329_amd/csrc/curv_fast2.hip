@@ -106,7 +106,12 @@ struct GramCfg {
   static constexpr int NUB = KB * (KB + 1) / 2;       // upper-triangular 16 x 16 blocks of K
   static constexpr int PPW = PREC == MOM_FP64 ? 2 : 4;
   static constexpr int ESZ = PREC == MOM_FP64 ? 8 : 4;
-  static constexpr size_t BYTES = ((size_t)ROWS * FLDX * ESZ + 15) & ~(size_t)15;
+  // bf16 moments stage the centred chunk as bf16 high and low parts, x ~ hi + lo, in two
+  // arrays of ROWS x FLDG (16-byte rows, the row stride of the range pass's bf16 copy)
+  static constexpr bool SPLIT = PREC == MOM_BF16;
+  static constexpr int FLDG = FCH + 8;
+  static constexpr size_t BYTES = SPLIT ? (size_t)2 * ROWS * FLDG * 2
+                                        : ((size_t)ROWS * FLDX * ESZ + 15) & ~(size_t)15;
 };
 
 template <int KMAX, int PREC>
@@ -134,7 +139,16 @@ __global__ __launch_bounds__(256) void curv_gram_kernel(const float* __restrict_
     }
     return;
   }
-  for (int t = lane; t < (C::ROWS - k) * FLDX; t += WAVE) XS[k * FLDX + t] = (ST)0;
+  uint16_t* XH = reinterpret_cast<uint16_t*>(smem_all + (size_t)gid * C::BYTES);   // split staging
+  uint16_t* XL = XH + C::ROWS * C::FLDG;
+  if constexpr (C::SPLIT) {
+    for (int t = lane; t < (C::ROWS - k) * C::FLDG; t += WAVE) {
+      XH[k * C::FLDG + t] = 0;
+      XL[k * C::FLDG + t] = 0;
+    }
+  } else {
+    for (int t = lane; t < (C::ROWS - k) * FLDX; t += WAVE) XS[k * FLDX + t] = (ST)0;
+  }
 
   AccT acc[C::NUB];
 #pragma unroll
@@ -143,6 +157,34 @@ __global__ __launch_bounds__(256) void curv_gram_kernel(const float* __restrict_
   bool nonfinite = false;
   // the MFMA pass over one staged chunk (K's upper-triangular 16 x 16 blocks)
   auto products = [&](int64_t c0) {
+    if constexpr (C::SPLIT) {
+      // K = sum over 32-column steps of hi hi^T + hi lo^T + lo hi^T on bf16 MFMA (products
+      // exact, float32 sums), plus lo lo^T on the diagonal blocks.  With x = hi + lo + r,
+      // |lo| <= 2^-8 |x| and |r| <= 2^-16 |x|, a product drops lo_i lo_j and the r terms, at
+      // most 3 * 2^-16 |x_i x_j|; on the diagonal blocks only the r terms, whose sign follows
+      // the second rounding, so the trace carries no one-sided error
+      const int ns = m - c0 >= FCH ? FCH / 32 : (int)((m - c0 + 31) / 32);
+      for (int st = 0; st < ns; ++st) {
+        const int col = 32 * st + 8 * (lane / 16);   // lane supplies columns col .. col + 7
+        shortx8 ah[KB], al[KB];
+#pragma unroll
+        for (int ab = 0; ab < KB; ++ab) {
+          ah[ab] = *reinterpret_cast<const shortx8*>(XH + (16 * ab + lane % 16) * C::FLDG + col);
+          al[ab] = *reinterpret_cast<const shortx8*>(XL + (16 * ab + lane % 16) * C::FLDG + col);
+        }
+        int b = 0;
+#pragma unroll
+        for (int ab = 0; ab < KB; ++ab)
+#pragma unroll
+          for (int bb = ab; bb < KB; ++bb, ++b) {
+            if (ab == bb) acc[b] = mfma16x16x32bf16(al[ab], al[bb], acc[b]);
+            acc[b] = mfma16x16x32bf16(ah[ab], al[bb], acc[b]);
+            acc[b] = mfma16x16x32bf16(al[ab], ah[bb], acc[b]);
+            acc[b] = mfma16x16x32bf16(ah[ab], ah[bb], acc[b]);
+          }
+      }
+      return;
+    }
     const int ng = m - c0 >= FCH ? FCH / 16 : (int)((m - c0 + 15) / 16);
     for (int g = 0; g < ng; ++g) {
       const int col = 16 * g + 4 * (lane / 16);      // lane supplies columns col .. col+3
@@ -249,7 +291,19 @@ __global__ __launch_bounds__(256) void curv_gram_kernel(const float* __restrict_
           const floatx4 xc = xv[t] - mean;
 #pragma unroll
           for (int e = 0; e < 4; ++e) tau64 = fma((double)xc[e], (double)xc[e], tau64);
-          *reinterpret_cast<floatx4*>(XS + (4 * t + g) * FLDX + 4 * c4) = xc;
+          if constexpr (C::SPLIT) {
+            uint16_t hi[4], lo[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              hi[e] = f2bf(xc[e]);
+              lo[e] = f2bf(xc[e] - bf2f(hi[e]));
+            }
+            const int o = (4 * t + g) * C::FLDG + 4 * c4;
+            *reinterpret_cast<uint2*>(XH + o) = make_uint2(hi[0] | ((uint32_t)hi[1] << 16), hi[2] | ((uint32_t)hi[3] << 16));
+            *reinterpret_cast<uint2*>(XL + o) = make_uint2(lo[0] | ((uint32_t)lo[1] << 16), lo[2] | ((uint32_t)lo[3] << 16));
+          } else {
+            *reinterpret_cast<floatx4*>(XS + (4 * t + g) * FLDX + 4 * c4) = xc;
+          }
         }
       wave_sync();
       if (c0 + FCH < m) load(c0 + FCH);
@@ -257,7 +311,9 @@ __global__ __launch_bounds__(256) void curv_gram_kernel(const float* __restrict_
       wave_sync();
     }
   }
-  // K (both triangles) to the workspace
+  // K (both triangles) to the workspace, each entry from the upper triangle: the split
+  // products sum a diagonal block's (x, y) and (y, x) terms in different orders, and the
+  // eigen-solve expects K exactly symmetric
   int b = 0;
 #pragma unroll
   for (int ab = 0; ab < KB; ++ab)
@@ -267,7 +323,7 @@ __global__ __launch_bounds__(256) void curv_gram_kernel(const float* __restrict_
       for (int r = 0; r < 4; ++r) {
         const int x = 16 * ab + (PREC == MOM_FP64 ? lane / 16 + 4 * r : 4 * (lane / 16) + r);
         const int y = 16 * bb + lane % 16;
-        if (x < k && y < k) {
+        if (x < k && y < k && x <= y) {
           Kout[x * KMAX + y] = (MomT<PREC>)acc[b][r];
           Kout[y * KMAX + x] = (MomT<PREC>)acc[b][r];
         }
@@ -404,7 +460,7 @@ __global__ __launch_bounds__(256) void curv_eigen_kernel(int64_t n, int64_t m, i
       fl |= PF_DEGENERATE;
     } else {
       const double smin = (double)A[ord[pe - 1] * C::JLD + ord[pe - 1]];
-      if (beyond_precision(sig0, smin, k, m, pe, PREC == MOM_FP64 ? 2 : (PREC == MOM_BF16 ? 1 : 0)))
+      if (beyond_precision(sig0, smin, k, m, pe, PREC == MOM_FP64 ? 2 : (PREC == MOM_BF16 ? 3 : 0)))
         fl |= PF_PRECISION_LIMIT;
     }
     reinterpret_cast<double*>(ws + L.off_ts)[i] = ts;

@@ -28,18 +28,21 @@ constexpr uint8_t PF_PRECISION_LIMIT = 128u;
 // Fast mode: whether the point's error estimate exceeds its precision's budget: bf16 moments
 // on rows narrower than 256 (their 8-bit products exceed 2e-2 on strongly curved patches
 // there), or a centred patch whose Gram matrix is too ill-conditioned for the moments.  The
-// moments' relative rounding u (2^-24 for float32 moments and the float32 Gram of the bf16
-// path, 2^-53 for float64) turns the weakest kept direction by about u cond, cond =
-// sigma_1 / sigma_pe, towards the null space, which moves the null-space term by that angle
-// spread over its q = m - pe directions: estimate 2 u cond / q (2 u cond when q = 0),
-// against the path's budget (1e-4 float32, 2e-2 bf16, 1e-6 float64).
+// Gram matrix's relative rounding u (prec_class 0: float32 moments, 2^-24; 1: bf16 moments
+// with a float32 Gram, 2^-24; 3: bf16 moments with the Gram from split bf16 products,
+// 3 * 2^-16, what a product of two hi + lo splits can drop; 2: float64, 2^-53) turns the
+// weakest kept direction by about u cond, cond = sigma_1 / sigma_pe, towards the null space,
+// which moves the null-space term by that angle spread over its q = m - pe directions:
+// estimate 2 u cond / q (2 u cond when q = 0), against the path's budget (1e-4 float32,
+// 2e-2 bf16, 1e-6 float64).
 __device__ __forceinline__ bool beyond_precision(double sig_max, double sig_min, int k, int64_t m, int pe,
                                                  int prec_class) {
   (void)k;
-  if (prec_class == 1 && m < 256) return true;
+  const bool bf16 = prec_class == 1 || prec_class == 3;
+  if (bf16 && m < 256) return true;
   if (!(sig_min > 0.0)) return pe > 0;
-  const double u = prec_class == 2 ? 0x1p-53 : 0x1p-24;
-  const double budget = prec_class == 0 ? 1e-4 : (prec_class == 1 ? 2e-2 : 1e-6);
+  const double u = prec_class == 2 ? 0x1p-53 : (prec_class == 3 ? 0x1.8p-15 : 0x1p-24);
+  const double budget = prec_class == 0 ? 1e-4 : (bf16 ? 2e-2 : 1e-6);
   const int64_t q = m - pe;
   return 2.0 * u * (sig_max / sig_min) / (double)(q > 0 ? q : 1) > budget;
 }

@@ -186,7 +186,8 @@ BF16_CASES = [("clusters", 900, 784, 11, 2061), ("torus", 1500, 256, 16, 3061), 
 @pytest.mark.parametrize("name,n,m,k,seed", BF16_CASES, ids=[f"{c[0]}-{c[1]}x{c[2]}-k{c[3]}" for c in BF16_CASES])
 @pytest.mark.parametrize("variant", ["paper", "haar"])
 def test_fast_bf16_parity(name, n, m, k, seed, variant):
-    """bf16 moments (float32 accumulation, float32 Gram) against the float64 oracle: 2e-2 bar."""
+    """bf16 moments (float32 accumulation; float32 Gram at k <= 12, Gram from split bf16
+    products at k >= 13) against the float64 oracle: 2e-2 bar."""
     import paper_2606_06329_amd as P
     from tests.gpu_common import TOL_LOW
     X, idx = _case(name, n, m, seed, k)

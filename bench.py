@@ -7,7 +7,7 @@ followed by mc_curvature_fast (Fast branch of Algorithm 1), inputs resident in
 HBM.  The headline workload is the largest configuration, the 50000 x 4096 blob
 mixture with k = 32: fp8 e4m3 distance GEMM with per-row scales and a float32
 re-rank of 64 candidates, Gram from split bf16 products (x = hi + lo), float32
-eigen-solve, bf16 range products.
+eigen-solve, range GEMM on binary16 operands (the bf16 curvature path).
 
 Prints ONE JSON line with the metric, a roofline entry for the dominant kernel
 (timed with the library's hipEvent stage timers on the launch stream), the
@@ -26,11 +26,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0, "fp64": 78.6}   # dense MFMA TFLOP/s, MI355X
+PEAK = {"fp32": 157.3, "bf16": 2500.0, "f16": 2500.0, "fp8": 5000.0, "fp64": 78.6}   # dense MFMA TFLOP/s, MI355X
 HBM_PEAK = 8000.0                                                      # GB/s
 # precision option -> (kNN GEMM precision, curvature moment precision, reported dtype)
-PRECISIONS = {"fp32": ("fp32", "fp32", "f32"), "bf16": ("bf16", "bf16", "bf16"),
-              "fp8": ("fp8", "bf16", "fp8/bf16"), "fp64": ("fp32", "fp64", "f32/f64")}
+# (the bf16 curvature path's two-pass form, k >= 13, runs its range GEMM on binary16)
+PRECISIONS = {"fp32": ("fp32", "fp32", "f32"), "bf16": ("bf16", "bf16", "bf16/f16"),
+              "fp8": ("fp8", "bf16", "fp8/bf16/f16"), "fp64": ("fp32", "fp64", "f32/f64")}
 # device sources of each kernel whose counters a profile summary records
 KERNEL_SOURCES = {
     "knn_gemm_topk": ("paper_2606_06329_amd/csrc/knn.hip", "paper_2606_06329_amd/csrc/mc_device.h"),
@@ -210,7 +211,10 @@ def roofline(P, stages, n, m, k, prec, workload):
         p = k - 1
         fv = 2.0 * k * p * m * n
         fg = 2.0 * k * m * (p * k / 2 + 2) * n
-        gp = PEAK["fp32" if cprec == "fp32" else ("fp64" if cprec == "fp64" else "bf16")]
+        # the G_tens GEMM: float32, float64, or binary16 operands on the bf16 path (the f16
+        # MFMA's dense peak equals bf16's)
+        gprec = cprec if cprec in ("fp32", "fp64") else "f16"
+        gp = PEAK[gprec]
         # the V_r^T product: float32 MFMA, float64 for float64 moments, and bf16 MFMA (high/low
         # parts) on the bf16 path with several waves per point (k > 16)
         vprec = "fp64" if cprec == "fp64" else ("bf16" if cprec == "bf16" and k > 16 else "fp32")
@@ -218,7 +222,7 @@ def roofline(P, stages, n, m, k, prec, workload):
         tmin = fv / (vp * 1e12) + fg / (gp * 1e12)
         cand["curv_range"] = (fv + fg, tmin,
                               f"per point 2k(k-1)m = {fv / n:.4g} flop ({vprec} MFMA) "
-                              f"+ 2km((k-1)k/2+2) = {fg / n:.4g} flop ({cprec} MFMA), x n = {fv + fg:.4g} per launch")
+                              f"+ 2km((k-1)k/2+2) = {fg / n:.4g} flop ({gprec} MFMA), x n = {fv + fg:.4g} per launch")
     if "curv_gram" in stages:
         f = float(k) * (k + 1) * m * n
         gprec = cprec if cprec in ("fp64", "bf16") else "fp32"
@@ -475,7 +479,8 @@ def main():
         "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": f"{args.workload} n={n} m={m} k={k}", "n": n, "m": m, "k": k,
-                   "precision": prec, "knn_gemm": kprec, "range_products": cprec, "variant": args.variant,
+                   "precision": prec, "knn_gemm": kprec,
+                   "range_products": "f16" if cprec == "bf16" and k >= 13 else cprec, "variant": args.variant,
                    "rerank": rerank, "candidates": rerank * k, "mode": "fast"},
         "roofline": roofline(P, stages, n, m, k, prec, args.workload),
         "stages_ms": stage_ms(stages),

@@ -145,7 +145,11 @@ int mc_knn(const float* X, int64_t n, int64_t m, int64_t ldx, int32_t k, int32_t
  *                combination is float64 in all three; the k x k eigen-solve is
  *                float32 Jacobi for MC_FP32 and MC_BF16, redone in float64 when a
  *                kept eigenvalue pair is near-degenerate (flag MC_PF_EIGEN_FP64),
- *                and float64 Jacobi for MC_FP64).  MC_FP64 centres
+ *                and float64 Jacobi for MC_FP64).  MC_BF16 at k >= 13 forms the Gram
+ *                matrix and V_r^T from split bf16 products (x = hi + lo) and runs the
+ *                third-moment GEMM on binary16 operands (patch rows scaled by powers of
+ *                two, packed binary16 pair products), float32 accumulation throughout;
+ *                at k <= 12 it takes bf16 operands with a float32 Gram.  MC_FP64 centres
  *                and accumulates in float64 (v_mfma_f64_16x16x4f64): use it for
  *                thin or noisy patches whose Gram matrix is ill-conditioned, where
  *                float32 moments lose digits.  k > MC_FAST_FP64_KMAX -> MC_ESHAPE.

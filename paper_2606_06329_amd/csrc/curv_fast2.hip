@@ -3,8 +3,8 @@
 //
 // What is computed is the Fast branch of Algorithm 1 (eqs. svd_cov, tA, tB, tnull,
 // fast_curv), evaluated as in curv_fast.hip's two-pass form:
-//   1. curv_gram:  K = X_c X_c^T on MFMA from one pass over the centred patch, and
-//                  tau (k-1) = ||X_c||_F^2 in float64.
+//   1. curv_gram:  K = X_c X_c^T on MFMA from one pass over the centred patch (split
+//                  bf16 products on the bf16 path), and tau (k-1) = ||X_c||_F^2 in float64.
 //   2. curv_eigen: the k x k eigen-solve of K (parallel-order Jacobi) gives
 //                  Ut = U_p diag(sigma_p^{-1/2}), the numerical rank and
 //                  (k-1) t_S = sum_l ||K ut_l||^2.  Float32 sweeps on the float32/bf16
@@ -15,7 +15,9 @@
 //                  X_c (k x chunk) x [V[:,l1] o V[:,l2] (l1 <= l2) | h | 1]
 //                  whose columns give G_tens, tr G_j = (X_c h)_j and r_j = (X_c 1)_j;
 //                  t_D = sum_c q_c h_c with q_c = sum_j X_c[j,c]^2; then the float64
-//                  combination.
+//                  combination.  On the bf16 path that GEMM runs on binary16 operands: the
+//                  patch rows scaled by powers of two from K's diagonal, and packed
+//                  binary16 products of the range rows.
 // Each stage runs at its own occupancy: the eigen-solve, a chain of dependent rounds, runs
 // one wave per point with only its two k x k matrices in LDS, so many points hide each
 // other's latency; the patch passes spread the staging of a chunk over all waves of a point.
@@ -107,7 +109,7 @@ struct GramCfg {
   static constexpr int PPW = PREC == MOM_FP64 ? 2 : 4;
   static constexpr int ESZ = PREC == MOM_FP64 ? 8 : 4;
   // bf16 moments stage the centred chunk as bf16 high and low parts, x ~ hi + lo, in two
-  // arrays of ROWS x FLDG (16-byte rows, the row stride of the range pass's bf16 copy)
+  // arrays of ROWS x FLDG (16-byte rows, the row stride of the range pass's 16-bit copy)
   static constexpr bool SPLIT = PREC == MOM_BF16;
   static constexpr int FLDG = FCH + 8;
   static constexpr size_t BYTES = SPLIT ? (size_t)2 * ROWS * FLDG * 2
@@ -506,18 +508,35 @@ struct RangeCfg {
   static constexpr size_t OFF_BJ = OFF_RED + (size_t)16 * NW * 8;          // tr G_j, r_j
   static constexpr size_t OFF_NB = OFF_BJ + (size_t)2 * KMAX * 8;
   static constexpr size_t OFF_PJ = OFF_NB + (size_t)KMAX * 4;
-  // bf16 moments: the staged patch rows again as bf16, the A operand of the range GEMM
+  static constexpr size_t OFF_RS = OFF_PJ + 2 * NPAD;                     // row scales 2^-e_j
+  // bf16 moments: the staged patch rows again as binary16 (row j scaled by 2^-e_j, below),
+  // the A operand of the range GEMM
   // (rows of FLDB = 72 elements: 144 bytes, so 16 lanes' 16-byte reads hit distinct banks)
   static constexpr int FLDB = FCH + 8;
   static constexpr size_t XB_B = BFA ? (((size_t)16 * KB * FLDB * 2 + 15) & ~(size_t)15) : 0;
-  static constexpr size_t OFF_XB = (OFF_PJ + 2 * NPAD + 15) & ~(size_t)15;
+  static constexpr size_t OFF_XB = (OFF_RS + (size_t)KMAX * 4 + 15) & ~(size_t)15;
   // XT[c][j] (high part, then low part): the B operand of the bf16 V_r^T product, K = j; rows of
   // FLDT = 40 elements (80 bytes: 16 lanes' 16-byte reads hit distinct banks)
   static constexpr int FLDT = 40;
   static constexpr size_t XT_B = VBF ? (size_t)2 * FCH * FLDT * 2 : 0;
   static constexpr size_t OFF_XT = OFF_XB + NBUF * XB_B;
   static constexpr size_t BYTES = OFF_XT + NBUF * XT_B;
+  // bf16 moments keep the range rows (and h, ones, zero) as binary16 in the VS buffers, rows of
+  // FLDH = 72 halves: the B operand of the range GEMM is formed by packed binary16 products
+  static constexpr int FLDH = FCH + 8;
+  static_assert(!BFA || (size_t)VROWS * FLDH * 2 <= VS_B, "binary16 range rows fit the VS buffer");
+  static_assert(!BFA || HREG, "bf16 moments form h in registers");
 };
+
+// Binary16 staging of the bf16 path's range GEMM: row j of the centred patch is scaled by
+// 2^-e_j, e_j the exponent with sqrt(K_jj) < 2^e_j (K_jj = ||X_c[j, :]||^2 from the Gram pass),
+// so every staged value has magnitude at most about 1; the range rows are scaled by 16, so
+// the pairwise products stay below 256.  The GEMM's row j is then rescaled by 2^(e_j - 8).
+__device__ __forceinline__ int range_row_exp(float kjj) {
+  int e = 0;
+  if (kjj > 0.0f) (void)frexpf(sqrtf(kjj), &e);
+  return e;
+}
 
 template <int KMAX, int PREC>
 struct RangeCfgSel {
@@ -576,8 +595,14 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
   const int ncol = npair + 2;
   const int nbr = (ncol + 15) / 16;                // column blocks in use
 
+  float* RSF = reinterpret_cast<float*>(sm + C::OFF_RS);   // binary16 row scales (bf16 moments)
+  const float* KD = reinterpret_cast<const float*>(ws + L.off_k) + (size_t)i * KMAX * KMAX;
+
   // ---- setup: neighbour rows, column tables, zero rows -----------------------------
-  if (tg < k) nb[tg] = idx[i * k + tg];            // checked by the Gram pass
+  if (tg < k) {
+    nb[tg] = idx[i * k + tg];                      // checked by the Gram pass
+    if constexpr (PREC == MOM_BF16) RSF[tg] = ldexpf(1.0f, -range_row_exp(KD[tg * KMAX + tg]));
+  }
   for (int t = tg; t < C::NPAD; t += C::NTG) {
     int a = C::VZERO, b = C::VZERO;                // padding column: zero row
     if (t < npair) {
@@ -607,6 +632,9 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
       }
     }
     for (int t = tg; t < FLDX; t += C::NTG) VS0[bf * VSE + C::VZERO * FLDX + t] = (ST)0;
+    if constexpr (PREC == MOM_BF16)
+      for (int t = tg; t < C::FLDH; t += C::NTG)
+        reinterpret_cast<uint16_t*>(VS0 + bf * VSE)[C::VZERO * C::FLDH + t] = 0;
   }
   // Ut^T operand of the V_r^T chunk product: A[l][j] = Ut[j][l] at row l = 16 lb + lane%16,
   // k index j = 16 jb + st + 4 (lane/16): the four lane groups read patch rows four apart,
@@ -646,8 +674,8 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
   for (int b = 0; b < C::NBW; ++b) {
     const int nbg = w + C::NW * b;
     const int pc = nbg * 16 + lane % 16 < C::NPAD ? nbg * 16 + lane % 16 : C::NPAD - 1;
-    off1[b] = pj1[pc] * FLDX;
-    off2[b] = pj2[pc] * FLDX;
+    off1[b] = pj1[pc] * (PREC == MOM_BF16 ? C::FLDH : FLDX);
+    off2[b] = pj2[pc] * (PREC == MOM_BF16 ? C::FLDH : FLDX);
   }
 
   // staging: lane (cl, g) of wave w holds rows g*RPG + r of column w*CPW + cl of the chunk
@@ -727,7 +755,7 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
           if constexpr (C::VBF) {
             const uint16_t hi = f2bf(xc);
             const uint16_t lo = f2bf(xc - __uint_as_float((uint32_t)hi << 16));
-            XB[j * C::FLDB + colw] = hi;
+            XB[j * C::FLDB + colw] = f2h(xc * RSF[j]);
             if constexpr (XT8) {
               th[r % 8] = (short)hi;
               tl[r % 8] = (short)lo;
@@ -737,7 +765,7 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
             }
           } else {
             XS[j * FLDX + colw] = xc;
-            if constexpr (PREC == MOM_BF16) XB[j * C::FLDB + colw] = f2bf(xc);
+            if constexpr (PREC == MOM_BF16) XB[j * C::FLDB + colw] = f2h(xc * RSF[j]);
           }
         }
       }
@@ -781,7 +809,7 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
         AccT v = AccT{0, 0, 0, 0};
         if constexpr (C::VBF) {
           // three bf16 products (high x low, low x high, high x high, the small terms first):
-          // Ut^T X_c to about 2^-16 of the terms, far inside the bf16 range products' 2^-9
+          // Ut^T X_c to about 2^-16 of the terms, far inside the binary16 range products' 2^-11
           const uint16_t* xt = XT + (16 * cb + lane % 16) * C::FLDT + 8 * (lane / 16);
           const shortx8 xh = *reinterpret_cast<const shortx8*>(xt);
           const shortx8 xl = *reinterpret_cast<const shortx8*>(xt + XTLO);
@@ -802,7 +830,10 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
         for (int r = 0; r < 4; ++r) {
           const int l = 16 * lb + (PREC == MOM_FP64 ? lane / 16 + 4 * r : 4 * (lane / 16) + r);
           const ST vr = (ST)v[r];
-          VS[l * FLDX + 16 * cb + lane % 16] = vr;
+          if constexpr (PREC == MOM_BF16)
+            reinterpret_cast<uint16_t*>(VS)[l * C::FLDH + 16 * cb + lane % 16] = f2h(16.0f * vr);
+          else
+            VS[l * FLDX + 16 * cb + lane % 16] = vr;
           hsum[t] += vr * vr;
         }
       }
@@ -826,8 +857,14 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
           }
           if (lane < 16) {
             const int col = 16 * vb + lane;
-            VS[C::VH * FLDX + col] = h;
-            VS[C::VONE * FLDX + col] = (c0 + col < m) ? (ST)1 : (ST)0;
+            if constexpr (PREC == MOM_BF16) {
+              uint16_t* VSh = reinterpret_cast<uint16_t*>(VS);
+              VSh[C::VH * C::FLDH + col] = f2h(16.0f * h);
+              VSh[C::VONE * C::FLDH + col] = (c0 + col < m) ? f2h(16.0f) : (uint16_t)0;
+            } else {
+              VS[C::VH * FLDX + col] = h;
+              VS[C::VONE * FLDX + col] = (c0 + col < m) ? (ST)1 : (ST)0;
+            }
             tD = fma((double)XS[C::XQ * FLDX + col], (double)h, tD);
           }
         }
@@ -886,56 +923,42 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
       const int ng = m - c0 >= FCH ? FCH / 16 : (int)((m - c0 + 15) / 16);
       for (int g = 0; g < ng; ++g) gstep(g);
     } else {
-      // bf16 operands, 32-column steps: lane l supplies columns 32 s + 8 (l / 16) + e
+      // binary16 operands, 32-column steps: lane l supplies columns 32 s + 8 (l / 16) + e; the
+      // A operand is the scaled patch, the B operand the pairwise products of the scaled range
+      // rows, eight per lane from four packed binary16 multiplies.  Both are stored as 16-bit
+      // integers and read as such (a binary16 pointer would not alias those stores).
+      const uint16_t* VSh = reinterpret_cast<const uint16_t*>(VS);
+      auto ld8 = [](const uint16_t* p) { return __builtin_bit_cast(halfx8, *reinterpret_cast<const shortx8*>(p)); };
       auto gstep = [&](int s32) {
         const int col0 = 32 * s32 + 8 * (lane / 16);
-        shortx8 abf[KB];
+        halfx8 ahf[KB];
 #pragma unroll
-        for (int a = 0; a < KB; ++a)
-          abf[a] = *reinterpret_cast<const shortx8*>(XB + (16 * a + lane % 16) * C::FLDB + col0);
+        for (int a = 0; a < KB; ++a) ahf[a] = ld8(XB + (16 * a + lane % 16) * C::FLDB + col0);
         if constexpr (C::NW == 2 || C::NW == 4) {
-          // the operand rows of blocks b + 1 .. b + PD are in flight while block b's products
-          // are formed (depths 2 to 4 measured no faster than 1)
+          // the operand rows of block b + 1 are in flight while block b's products are formed
           constexpr int PD = 1, RING = PD + 1;
-          floatx4 pq[RING][4];
-          auto rd = [&](floatx4 (&d)[4], int b) {
-            const ST* r1 = VS + off1[b] + col0;
-            const ST* r2 = VS + off2[b] + col0;
-            d[0] = *reinterpret_cast<const floatx4*>(r1);
-            d[1] = *reinterpret_cast<const floatx4*>(r1 + 4);
-            d[2] = *reinterpret_cast<const floatx4*>(r2);
-            d[3] = *reinterpret_cast<const floatx4*>(r2 + 4);
+          halfx8 pq[RING][2];
+          auto rd = [&](halfx8 (&d)[2], int b) {
+            d[0] = ld8(VSh + off1[b] + col0);
+            d[1] = ld8(VSh + off2[b] + col0);
           };
 #pragma unroll
           for (int b = 0; b < PD && b < C::NBW; ++b) rd(pq[b], b);
 #pragma unroll
           for (int b = 0; b < C::NBW; ++b) {
             if (b + PD < C::NBW) rd(pq[(b + PD) % RING], b + PD);
-            const floatx4(&cur)[4] = pq[b % RING];
-            shortx8 bbf;
+            const halfx8 bv = pq[b % RING][0] * pq[b % RING][1];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              bbf[e] = (short)f2bf(cur[0][e] * cur[2][e]);
-              bbf[4 + e] = (short)f2bf(cur[1][e] * cur[3][e]);
-            }
-#pragma unroll
-            for (int a = 0; a < KB; ++a) acc[a][b] = mfma16x16x32bf16(abf[a], bbf, acc[a][b]);
+            for (int a = 0; a < KB; ++a) acc[a][b] = mfma16x16x32f16(ahf[a], bv, acc[a][b]);
           }
         } else {
 #pragma unroll
           for (int b = 0; b < C::NBW; ++b) {
-            const floatx4 p0 = *reinterpret_cast<const floatx4*>(VS + off1[b] + col0);
-            const floatx4 p1 = *reinterpret_cast<const floatx4*>(VS + off1[b] + col0 + 4);
-            const floatx4 q0 = *reinterpret_cast<const floatx4*>(VS + off2[b] + col0);
-            const floatx4 q1 = *reinterpret_cast<const floatx4*>(VS + off2[b] + col0 + 4);
-            shortx8 bbf;
+            const halfx8 p = ld8(VSh + off1[b] + col0);
+            const halfx8 q = ld8(VSh + off2[b] + col0);
+            const halfx8 bv = p * q;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              bbf[e] = (short)f2bf(p0[e] * q0[e]);
-              bbf[4 + e] = (short)f2bf(p1[e] * q1[e]);
-            }
-#pragma unroll
-            for (int a = 0; a < KB; ++a) acc[a][b] = mfma16x16x32bf16(abf[a], bbf, acc[a][b]);
+            for (int a = 0; a < KB; ++a) acc[a][b] = mfma16x16x32f16(ahf[a], bv, acc[a][b]);
           }
         }
       };
@@ -946,6 +969,18 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
     if constexpr (C::NBUF == 1) gsync<C::NW>();
   }
   gsync<C::NW>();
+  if constexpr (PREC == MOM_BF16) {
+    // undo the binary16 scales: row j of the GEMM by 2^(e_j - 8)
+#pragma unroll
+    for (int a = 0; a < KB; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = 16 * a + 4 * (lane / 16) + r;
+        const float sc = j < k ? 1.0f / (256.0f * RSF[j]) : 0.0f;   // 2^(e_j - 8), exact
+#pragma unroll
+        for (int b = 0; b < C::NBW; ++b) acc[a][b][r] *= sc;
+      }
+  }
 
   // ---- reductions: raw sums (k-1) * (t_range, g, t_A, t_S, t_D) ------------------------
   double part[5] = {0.0, 0.0, 0.0, 0.0, tD};

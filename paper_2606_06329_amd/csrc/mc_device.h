@@ -12,6 +12,7 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef short shortx8 __attribute__((ext_vector_type(8)));
 typedef short shortx4 __attribute__((ext_vector_type(4)));
 typedef int intx8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
 constexpr int WAVE = 64;
 
@@ -73,6 +74,9 @@ __device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(ui
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
+// Round-to-nearest-even float -> IEEE binary16 bits.
+__device__ __forceinline__ uint16_t f2h(float f) { return __builtin_bit_cast(uint16_t, (_Float16)f); }
+
 // D(16x16) += A(16x4) * B(4x16), fp32.  Lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; it receives D[4*(l/16)+r][l%16], r = 0..3.
 __device__ __forceinline__ floatx4 mfma16x16x4(float a, float b, floatx4 c) {
@@ -92,8 +96,13 @@ __device__ __forceinline__ floatx16 mfma32x32x2(float a, float b, floatx16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
-// D(16x16) += A(16x32) * B(32x16), bf16 in, fp32 accumulate.  Lane l supplies
+// D(16x16) += A(16x32) * B(32x16), binary16 in, fp32 accumulate.  Lane l supplies
 // A[l%16][8*(l/16)+e] and B[8*(l/16)+e][l%16], e = 0..7.
+__device__ __forceinline__ floatx4 mfma16x16x32f16(halfx8 a, halfx8 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+// D(16x16) += A(16x32) * B(32x16), bf16 in, fp32 accumulate, operands as the binary16 form.
 __device__ __forceinline__ floatx4 mfma16x16x32bf16(shortx8 a, shortx8 b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(__attribute__((ext_vector_type(8))) __bf16, a),
                                                  __builtin_bit_cast(__attribute__((ext_vector_type(8))) __bf16, b),

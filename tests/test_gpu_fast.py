@@ -201,6 +201,29 @@ def test_fast_bf16_parity(name, n, m, k, seed, variant):
     assert err.max() <= TOL_LOW
 
 
+# The two-pass form (k >= 13) on the bf16 path: Gram from split bf16 products, V_r^T from
+# split bf16 products, the range GEMM on binary16 operands with power-of-two row scales.  Its
+# curvatures hold the float32 bar on these wide-row patches; the 2e-2 budget above is looser
+# than any of its roundings, so this bar guards each of them (a wrong scale or operand moves
+# t_range, g and t_A, terms small beside tau, by far more than 1e-4 of kappa).
+BF16_TWO_PASS = [("torus", 1500, 256, 16, 3061), ("torus", 800, 300, 20, 3062), ("blobs", 500, 1024, 32, 5061)]
+
+
+@pytest.mark.parametrize("name,n,m,k,seed", BF16_TWO_PASS, ids=[f"{c[0]}-{c[1]}x{c[2]}-k{c[3]}" for c in BF16_TWO_PASS])
+@pytest.mark.parametrize("variant", ["paper", "haar"])
+def test_fast_bf16_two_pass_tight(name, n, m, k, seed, variant):
+    import paper_2606_06329_amd as P
+    X, idx = _case(name, n, m, seed, k)
+    kap, fl = P.curvature_fast(to_dev(X), to_dev_idx(idx), variant, "bf16")
+    kap, fl = kap.cpu().numpy(), fl.cpu().numpy()
+    want, pe = oracle_fast(X, idx, variant)
+    okr = ((fl & 4) == 0) & ((fl & 128) == 0) & (pe == min(k - 1, m))
+    err = rel_err(kap, want)[okr]
+    print(f"bf16 two-pass {name} k={k} {variant}: max {err.max():.2e} median {np.median(err):.2e}")
+    assert okr.mean() > 0.95
+    assert err.max() <= TOL_FP32
+
+
 def _degenerate_integer_patch(m=256):
     """Eight points whose centred Gram matrix has the eigenvalues 8 s_j^2, s = (1, 1, 2, 3, 4,
     5, 6), plus 0: rows of an 8 x 8 Hadamard matrix without its first column, column j scaled

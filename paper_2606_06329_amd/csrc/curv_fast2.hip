@@ -927,13 +927,16 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
       // A operand is the scaled patch, the B operand the pairwise products of the scaled range
       // rows, eight per lane from four packed binary16 multiplies.  Both are stored as 16-bit
       // integers and read as such (a binary16 pointer would not alias those stores).
-      const uint16_t* VSh = reinterpret_cast<const uint16_t*>(VS);
+      // The lane's column part 8 (l / 16) goes into the bases and the two steps are unrolled, so
+      // a step's column offset is an immediate of the LDS reads.
+      const uint16_t* VSh = reinterpret_cast<const uint16_t*>(VS) + 8 * (lane / 16);
+      const uint16_t* XBl = XB + 8 * (lane / 16);
       auto ld8 = [](const uint16_t* p) { return __builtin_bit_cast(halfx8, *reinterpret_cast<const shortx8*>(p)); };
       auto gstep = [&](int s32) {
-        const int col0 = 32 * s32 + 8 * (lane / 16);
+        const int col0 = 32 * s32;
         halfx8 ahf[KB];
 #pragma unroll
-        for (int a = 0; a < KB; ++a) ahf[a] = ld8(XB + (16 * a + lane % 16) * C::FLDB + col0);
+        for (int a = 0; a < KB; ++a) ahf[a] = ld8(XBl + (16 * a + lane % 16) * C::FLDB + col0);
         if constexpr (C::NW == 2 || C::NW == 4) {
           // the operand rows of block b + 1 are in flight while block b's products are formed
           constexpr int PD = 1, RING = PD + 1;
@@ -963,7 +966,9 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
         }
       };
       const int st32 = m - c0 >= FCH ? FCH / 32 : (int)((m - c0 + 31) / 32);
-      for (int s32 = 0; s32 < st32; ++s32) gstep(s32);
+#pragma unroll
+      for (int s32 = 0; s32 < FCH / 32; ++s32)
+        if (s32 < st32) gstep(s32);
     }
     // single buffers: the next chunk's staging overwrites what this GEMM reads
     if constexpr (C::NBUF == 1) gsync<C::NW>();

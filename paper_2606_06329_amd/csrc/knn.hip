@@ -1308,19 +1308,38 @@ __global__ __launch_bounds__(256) void knn_collect_kernel(const float* __restric
       const float4 nr4 = *reinterpret_cast<const float4*>(&q_n[1][rb]);
       const float thrv[4] = {thr4.x, thr4.y, thr4.z, thr4.w};
       const float nrv[4] = {nr4.x, nr4.y, nr4.z, nr4.w};
+      // candidates r for query c: the 32 lanes of a half wave share c, so their hits take one
+      // counter increment per half wave, each lane writing at the base plus its rank among
+      // the half wave's hits (in e4, then lane order)
+      const unsigned hsh = lane_id() & 32u;                 // 0 or 32: the half wave
+      const uint64_t below = ((1ull << (lane_id() & 31u)) - 1ull) << hsh;
+      bool hit[4];
+      int rank[4], tot = 0;
 #pragma unroll
       for (int e4 = 0; e4 < 4; ++e4) {
         const int r = rb + e4;
         const int64_t qr = rt * KBQ + r;
         const float s = sv[e4];
-        // candidate r for query c
-        if (s <= thc && qc < n && qr < n) {
-          const float lb = sqrtf(fmaxf(0.0f, s + q_a[0][c])) * (1.0f - 0x1p-22f) - q_e[1][r];
-          if (lb <= q_T[0][c]) {
-            const int slot = atomicAdd(rs.cnt + qc, 1);
-            if (slot < RESCAN_CMAX) rs.cbuf[qc * RESCAN_CMAX + slot] = (int)qr;
-          }
-        }
+        bool h = s <= thc && qc < n && qr < n;
+        if (h) h = sqrtf(fmaxf(0.0f, s + q_a[0][c])) * (1.0f - 0x1p-22f) - q_e[1][r] <= q_T[0][c];
+        const uint64_t mk = __ballot(h);
+        hit[e4] = h;
+        rank[e4] = tot + (int)__popcll(mk & below);
+        tot += (int)__popcll((mk >> hsh) & 0xFFFFFFFFull);
+      }
+      int base = 0;
+      if ((lane_id() & 31u) == 0 && tot > 0) base = atomicAdd(rs.cnt + qc, tot);
+      base = __shfl(base, (int)hsh, WAVE);
+#pragma unroll
+      for (int e4 = 0; e4 < 4; ++e4) {
+        const int slot = base + rank[e4];
+        if (hit[e4] && slot < RESCAN_CMAX) rs.cbuf[qc * RESCAN_CMAX + slot] = (int)(rt * KBQ + rb + e4);
+      }
+#pragma unroll
+      for (int e4 = 0; e4 < 4; ++e4) {
+        const int r = rb + e4;
+        const int64_t qr = rt * KBQ + r;
+        const float s = sv[e4];
         // candidate c for query r (off-diagonal tiles): re-associate the stored score
         if (t < PB && qr < n && qc < n) {
           const float thr = thrv[e4];

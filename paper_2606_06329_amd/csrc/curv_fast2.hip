@@ -252,13 +252,25 @@ __global__ __launch_bounds__(256) void curv_gram_kernel(const float* __restrict_
       const int r = __shfl(nbv, j < k ? j : 0, WAVE);
       rp[t] = X + (int64_t)r * ldx;
     }
+    // Two instances of the pass: FULL when k fills the bucket (no row tests), and the
+    // general one.  A chunk that lies inside the rows (and 16-byte rows) is gathered with
+    // unconditional vector loads, rows j >= k reading row 0 and being zeroed after the load.
     floatx4 xv[RT];
-    auto load = [&](int64_t c0) {
+    auto load = [&](int64_t c0, auto full_tag) {
+      constexpr bool FULL = decltype(full_tag)::value;
       const int64_t c = c0 + 4 * c4;
+      if (vec && c0 + FCH <= m) {
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          const floatx4 v = *reinterpret_cast<const floatx4*>(rp[t] + c);
+          xv[t] = (FULL || 4 * t + g < k) ? v : floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+        return;
+      }
 #pragma unroll
       for (int t = 0; t < RT; ++t) {
         floatx4 v = {0.f, 0.f, 0.f, 0.f};
-        if (4 * t + g < k) {
+        if (FULL || 4 * t + g < k) {
           if (vec && c + 3 < m) {
             v = *reinterpret_cast<const floatx4*>(rp[t] + c);
           } else {
@@ -270,14 +282,16 @@ __global__ __launch_bounds__(256) void curv_gram_kernel(const float* __restrict_
         xv[t] = v;
       }
     };
-    load(0);
+    auto pass = [&](auto full_tag) {
+    constexpr bool FULL = decltype(full_tag)::value;
+    load(0, full_tag);
     for (int64_t c0 = 0; c0 < m; c0 += FCH) {
       floatx4 x0, sm = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int e = 0; e < 4; ++e) x0[e] = __shfl(xv[0][e], c4, WAVE);   // row 0 sits in group 0
 #pragma unroll
       for (int t = 0; t < RT; ++t)
-        if (4 * t + g < k) {
+        if (FULL || 4 * t + g < k) {
           xv[t] -= x0;
           sm += xv[t];
         }
@@ -289,7 +303,7 @@ __global__ __launch_bounds__(256) void curv_gram_kernel(const float* __restrict_
       const floatx4 mean = sm / (float)k;
 #pragma unroll
       for (int t = 0; t < RT; ++t)
-        if (4 * t + g < k) {
+        if (FULL || 4 * t + g < k) {
           const floatx4 xc = xv[t] - mean;
 #pragma unroll
           for (int e = 0; e < 4; ++e) tau64 = fma((double)xc[e], (double)xc[e], tau64);
@@ -308,10 +322,13 @@ __global__ __launch_bounds__(256) void curv_gram_kernel(const float* __restrict_
           }
         }
       wave_sync();
-      if (c0 + FCH < m) load(c0 + FCH);
+      if (c0 + FCH < m) load(c0 + FCH, full_tag);
       products(c0);
       wave_sync();
     }
+    };
+    if (k == KMAX) pass(std::true_type{});
+    else pass(std::false_type{});
   }
   // K (both triangles) to the workspace, each entry from the upper triangle: the split
   // products sum a diagonal block's (x, y) and (y, x) terms in different orders, and the

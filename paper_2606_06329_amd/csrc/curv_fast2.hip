@@ -709,25 +709,27 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
   uint16_t* XB = XB0;
   uint16_t* XT = XT0;
   float xr[C::RPG];
+  // unconditional gather (rows j >= k read row nbr_ = 0, columns past m the last column, both
+  // in bounds); the staging zeroes those entries where it uses them, so nothing waits for
+  // this chunk's loads before the products that run behind them
   auto load = [&](int64_t c0) {
     const int64_t c = c0 + colw;
+    const int64_t cc = c < m ? c : m - 1;
 #pragma unroll
-    for (int r = 0; r < C::RPG; ++r) {
-      const int j = grp * C::RPG + r;
-      xr[r] = (j < k && c < m) ? X[(int64_t)nbr_[r] * ldx + c] : 0.0f;
-    }
+    for (int r = 0; r < C::RPG; ++r) xr[r] = X[(int64_t)nbr_[r] * ldx + cc];
   };
   // the centred chunk: offsets from the first row, minus their mean (as centre_column), and
   // q_c = sum_j X_c[j, c]^2, reduced over the lanes that share the column
   auto stage = [&](int64_t c0) {
     if constexpr (PREC == MOM_FP64) {
+      const bool cin = c0 + colw < m;
       const double x0 = (double)__shfl(xr[0], cl, WAVE);
       double d[C::RPG];
       double s = 0.0;
 #pragma unroll
       for (int r = 0; r < C::RPG; ++r) {
         const int j = grp * C::RPG + r;
-        d[r] = j < k ? (double)xr[r] - x0 : 0.0;
+        d[r] = (j < k && cin) ? (double)xr[r] - x0 : 0.0;
         s += d[r];
       }
 #pragma unroll
@@ -747,13 +749,14 @@ __attribute__((amdgpu_waves_per_eu(RangeCfgSel<KMAX, PREC>::WPE, 8))) void curv_
       for (int o = C::CPW; o < WAVE; o <<= 1) q += __shfl_xor(q, o, WAVE);
       if (grp == 0) XS[C::XQ * FLDX + colw] = q;
     } else {
+      const bool cin = c0 + colw < m;
       const float x0 = group_bcast_f<C::CPW>(xr[0]);
       float d[C::RPG];
       float s = 0.0f;
 #pragma unroll
       for (int r = 0; r < C::RPG; ++r) {
         const int j = grp * C::RPG + r;
-        d[r] = j < k ? xr[r] - x0 : 0.0f;
+        d[r] = (j < k && cin) ? xr[r] - x0 : 0.0f;
         s += d[r];
       }
       s = group_sum_f<C::CPW>(s);

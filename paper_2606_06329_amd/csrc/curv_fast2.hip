@@ -254,17 +254,15 @@ __global__ __launch_bounds__(256) void curv_gram_kernel(const float* __restrict_
     }
     // Two instances of the pass: FULL when k fills the bucket (no row tests), and the
     // general one.  A chunk that lies inside the rows (and 16-byte rows) is gathered with
-    // unconditional vector loads, rows j >= k reading row 0 and being zeroed after the load.
+    // unconditional vector loads; rows j >= k read row 0 and are never used (the centring,
+    // tau and the staging skip them), so nothing waits for the loads before the products.
     floatx4 xv[RT];
     auto load = [&](int64_t c0, auto full_tag) {
       constexpr bool FULL = decltype(full_tag)::value;
       const int64_t c = c0 + 4 * c4;
       if (vec && c0 + FCH <= m) {
 #pragma unroll
-        for (int t = 0; t < RT; ++t) {
-          const floatx4 v = *reinterpret_cast<const floatx4*>(rp[t] + c);
-          xv[t] = (FULL || 4 * t + g < k) ? v : floatx4{0.f, 0.f, 0.f, 0.f};
-        }
+        for (int t = 0; t < RT; ++t) xv[t] = *reinterpret_cast<const floatx4*>(rp[t] + c);
         return;
       }
 #pragma unroll

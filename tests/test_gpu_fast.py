@@ -23,6 +23,8 @@ CASES = [
     ("swissroll", 700, 97, 5, 4012),      # ragged m, small k
     ("torus", 800, 200, 20, 3012),        # two waves per point
     ("blobs", 600, 300, 32, 5011),        # k = 32, four waves per point
+    ("torus", 700, 150, 14, 3014),        # two-pass form, k below its bucket of 16
+    ("blobs", 500, 200, 30, 5014),        # k below its bucket of 32, ragged chunk
 ]
 
 
@@ -206,7 +208,8 @@ def test_fast_bf16_parity(name, n, m, k, seed, variant):
 # curvatures hold the float32 bar on these wide-row patches; the 2e-2 budget above is looser
 # than any of its roundings, so this bar guards each of them (a wrong scale or operand moves
 # t_range, g and t_A, terms small beside tau, by far more than 1e-4 of kappa).
-BF16_TWO_PASS = [("torus", 1500, 256, 16, 3061), ("torus", 800, 300, 20, 3062), ("blobs", 500, 1024, 32, 5061)]
+BF16_TWO_PASS = [("torus", 1500, 256, 16, 3061), ("torus", 800, 300, 20, 3062), ("blobs", 500, 1024, 32, 5061),
+                 ("torus", 900, 256, 14, 3063), ("blobs", 500, 1024, 30, 5063)]
 
 
 @pytest.mark.parametrize("name,n,m,k,seed", BF16_TWO_PASS, ids=[f"{c[0]}-{c[1]}x{c[2]}-k{c[3]}" for c in BF16_TWO_PASS])
